@@ -1,0 +1,229 @@
+"""Time-to-tolerance benchmark of the s-step PCG hot path on one MI355X.
+
+Workload: 3D 27-point variable-coefficient diffusion on a 192^3 grid
+(n = 7,077,888, nnz = 189,119,224), coefficients log-uniform over
+[1e-2, 1e2] on 8^3 blocks, b ~ N(0,1), Jacobi preconditioner, s = 6, two FGS
+sweeps, Chebyshev interval from 20-step Lanczos, tolerance 1e-8.  All inputs
+are seeded and synthetic.
+
+One step = one FP64 s-step PCG solve to tolerance plus one mixed-precision
+(FP32 inner, FP64 refinement) solve to the same tolerance, inputs resident in
+HBM.  `value` is the FP64 time to tolerance (median over the timed steps).
+The roofline object covers the matrix powers kernel (the SpMV launches with
+the fused Chebyshev/Jacobi epilogue), timed by HIP events around that phase
+of every outer iteration inside the timed solves.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "time to rel-res 1e-8 (FP64 vs mixed) + HBM GB/s, 27-pt 192^3, 1 GPU"
+
+
+def log(msg: str) -> None:
+    print(msg, file=sys.stderr, flush=True)
+
+
+def spmv_family_bytes(n: int, nnz: int, s: int, elem: int) -> float:
+    """Algorithmic bytes of one matrix powers kernel (s SpMV launches).
+
+    Per SpMV: values + column indices (elem + 4 per nonzero), the input
+    vector read once and the output written once (2 n elem).  Epilogue of
+    launch q < s: dinv read and z_{q+1} written (2 n elem), plus z_{q-1} read
+    for q >= 2 (n elem).  Padding of the sliced layout is not counted.
+    """
+    per_spmv = (elem + 4) * nnz + 2 * n * elem
+    epi = sum((2 if q == 1 else 3) * n * elem for q in range(1, s))
+    return s * per_spmv + epi
+
+
+def phase_bytes(n: int, s: int, elem: int) -> dict:
+    """Algorithmic bytes of the other phases per launch."""
+    return {
+        "gram_update": (6 * s + 1) * n * elem,   # read Z, Q, AZ, AQ, r; write Q, AQ
+        "gram_rect": 2 * s * n * elem,           # read Q, AZ
+        "xr": (2 * s + 6) * n * elem,            # read x, Q, r, AQ, dinv; write x, r, z1
+    }
+
+
+def build_workload(N: int):
+    import sspcg_inputs as si
+    t0 = time.time()
+    A = si.stencil("27pt", N, si.coeff_blocks(N))
+    b = si.rhs_normal(A.n)
+    t1 = time.time()
+    interval = si.lanczos_bounds(A)
+    log(f"[bench] workload 27pt {N}^3: n={A.n} nnz={A.nnz} assembly {t1 - t0:.1f}s, "
+        f"lanczos {time.time() - t1:.1f}s, interval {interval}")
+    return A, b, interval
+
+
+def cpu_baseline(A, b, interval, s, sweeps, outer_iters_gpu, sample_outer):
+    """The oracle on the host, on a bounded sample of the same solve."""
+    import oracle
+    oracle.build()
+    t0 = time.time()
+    _, res = oracle.sspcg(A, b, s=s, sweeps=sweeps, interval=interval, tol=1e-30,
+                          max_outer=sample_outer)
+    dt = time.time() - t0
+    per_outer = dt / max(res["iters"], 1)
+    return {
+        "value": per_outer * outer_iters_gpu, "unit": "s", "cores": oracle.threads(),
+        "kind": "oracle",
+        "sample": (f"{res['iters']} outer iterations of the FP64 s-step solve on the same "
+                   f"system ({dt:.1f} s wall, setup included), scaled by the GPU's "
+                   f"{outer_iters_gpu} outer iterations to tolerance"),
+        "seconds_per_outer": per_outer,
+    }
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--N", type=int, default=192)
+    ap.add_argument("--s", type=int, default=6)
+    ap.add_argument("--sweeps", type=int, default=2)
+    ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-outer", type=int, default=4)
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-profile", action="store_true",
+                    help="time without the per-phase HIP events")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus} GPUs, WORLD_SIZE={world}): "
+              "this build measures the single-GPU hot path; multi-GPU sharding is not built.",
+              file=sys.stderr)
+        return 2
+
+    import torch
+    import paper_2603_09790_amd as P
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 1
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    A, b_np, interval = build_workload(args.N)
+    t0 = time.time()
+    M = P.Matrix.from_csr(A, fp32=not args.no_mixed, device=dev)
+    info_m = M.info()
+    log(f"[bench] matrix on device in {time.time() - t0:.1f}s: slots {info_m['slots']} "
+        f"(padding {info_m['slots'] / A.nnz - 1:.4f}), {info_m['device_bytes'] / 1e9:.2f} GB")
+    b = torch.from_numpy(b_np).to(dev)
+    opts = dict(s=args.s, sweeps=args.sweeps, interval=interval, tol=args.tol,
+                profile=not args.no_profile)
+
+    def step():
+        x64, i64 = P.solve(M, b, **opts)
+        imx = None
+        if not args.no_mixed:
+            _, imx = P.solve(M, b, precision="mixed", **opts)
+        return x64, i64, imx
+
+    for w in range(args.warmup):
+        _, i64, imx = step()
+        log(f"[bench] warmup {w}: fp64 {i64['device_ms']:.1f} ms {i64['outer_iters']} outer "
+            f"{i64['status_name']}" + ("" if imx is None else
+                                       f"; mixed {imx['device_ms']:.1f} ms "
+                                       f"{imx['refinements']} refinements"))
+    torch.cuda.synchronize()
+    recs = []
+    t_start = time.time()
+    for k in range(args.steps):
+        torch.cuda.synchronize()
+        ts = time.time()
+        x64, i64, imx = step()
+        torch.cuda.synchronize()
+        recs.append((time.time() - ts, i64, imx))
+        log(f"[bench] step {k}: wall {recs[-1][0]:.3f}s fp64 {i64['device_ms']:.1f} ms "
+            f"({i64['outer_iters']} outer, relres {i64['relres']:.2e})"
+            + ("" if imx is None else f", mixed {imx['device_ms']:.1f} ms "
+               f"({imx['refinements']} refinements, {imx['outer_iters']} inner)"))
+    torch.cuda.synchronize()
+    total = time.time() - t_start
+
+    fp64_s = float(np.median([r[1]["device_ms"] for r in recs])) / 1e3
+    last = recs[-1][1]
+    n, nnz, s = A.n, A.nnz, args.s
+    out = {
+        "metric": METRIC, "value": fp64_s, "unit": "s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * total / args.steps,
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"27-point variable-coefficient diffusion {args.N}^3, "
+                               "log-uniform k in [1e-2,1e2] on 8^3 blocks, b~N(0,1), Jacobi",
+                   "n": n, "nnz": nnz, "s": s, "sweeps": args.sweeps, "tol": args.tol,
+                   "interval": list(interval), "layout_slots": info_m["slots"]},
+        "fp64": {"time_s": fp64_s, "outer_iters": last["outer_iters"], "relres": last["relres"],
+                 "status": last["status_name"]},
+    }
+    if not args.no_mixed:
+        mx_s = float(np.median([r[2]["device_ms"] for r in recs])) / 1e3
+        lm = recs[-1][2]
+        out["mixed"] = {"time_s": mx_s, "refinements": lm["refinements"],
+                        "inner_iters": lm["outer_iters"], "relres_true": lm["relres"],
+                        "speedup_vs_fp64": fp64_s / mx_s, "status": lm["status_name"]}
+    if not args.no_profile:
+        pr = last["profile"]
+        sp = pr["spmv"]
+        mpk_calls = sp["launches"] / s
+        b_mpk = spmv_family_bytes(n, nnz, s, 8)
+        achieved = b_mpk * mpk_calls / (sp["ms"] / 1e3) / 1e9
+        out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                           "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                           "kernel": "k_spmv (matrix powers kernel, FP64)",
+                           "avg_launch_us": 1e3 * sp["ms"] / sp["launches"],
+                           "bytes_per_launch": b_mpk / s}
+        pb = phase_bytes(n, s, 8)
+        phases = {}
+        tot_b, tot_ms = 0.0, 0.0
+        for ph in ("spmv", "gram_update", "gram_rect", "xr"):
+            e = pr[ph]
+            if e["launches"] == 0:
+                continue
+            nb = (b_mpk / s if ph == "spmv" else pb[ph]) * e["launches"]
+            phases[ph] = {"launches": e["launches"], "ms": e["ms"],
+                          "gbs": nb / (e["ms"] / 1e3) / 1e9}
+            tot_b += nb
+            tot_ms += e["ms"]
+        for ph in ("fgs", "norm"):
+            phases[ph] = {"launches": pr[ph]["launches"], "ms": pr[ph]["ms"]}
+        out["phases"] = phases
+        out["hbm_gbs_spmv_gram"] = (sum(phases[p]["gbs"] * phases[p]["ms"] for p in
+                                        ("spmv", "gram_update", "gram_rect") if p in phases)
+                                    / sum(phases[p]["ms"] for p in ("spmv", "gram_update",
+                                                                     "gram_rect") if p in phases))
+        out["hbm_gbs_all_streaming"] = tot_b / (tot_ms / 1e3) / 1e9
+        out["profiled_ms_total"] = sum(pr[p]["ms"] for p in L_PHASES)
+    # classical PCG comparator on the same system (outside the timed steps)
+    _, ip = P.pcg(M, b, tol=args.tol)
+    out["pcg"] = {"time_s": ip["device_ms"] / 1e3, "iters": ip["outer_iters"],
+                  "relres": ip["relres"]}
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline(A, b_np, interval, s, args.sweeps,
+                                           last["outer_iters"], args.cpu_sample_outer)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+L_PHASES = ["spmv", "gram_update", "gram_rect", "fgs", "norm", "xr"]
+
+if __name__ == "__main__":
+    sys.exit(main())

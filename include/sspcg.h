@@ -1,0 +1,260 @@
+/* sspcg.h - C ABI of the MI355X (gfx950) s-step PCG library (libsspcg.so).
+ *
+ * The library solves A x = b for a sparse symmetric positive definite A in
+ * CSR form with the s-step preconditioned conjugate gradient method of
+ * D'Ambra, Bernaschi, Carrozzo and Thomas, "Scalable s-step Preconditioned
+ * Conjugate Gradient with Chebyshev Basis and Gauss-Seidel Gram Solve"
+ * (arXiv 2603.09790): Algorithm 1 (outer iteration), Algorithm 2 (matrix
+ * powers kernel, MPK, for the Chebyshev basis) and the Forward Gauss-Seidel
+ * (FGS) iteration of Sec. 3.1 for the two reduced s x s Gram systems.  The
+ * preconditioner is Jacobi, M = diag(A).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Pointers named in a "device" argument are HIP device addresses; all
+ *   others are host addresses.  Device buffers are owned by the caller and
+ *   must stay alive until the work that uses them has finished on `stream`.
+ * - `stream` is a hipStream_t passed as a plain pointer; NULL selects the
+ *   default stream.  Kernel-level calls only enqueue work and return; the
+ *   solve calls block until the solve has finished.
+ * - Indices are int32 (n and nnz below 2^31).  Floating point is IEEE binary64
+ *   unless a call says otherwise.  Device pointers must be aligned to their
+ *   element size (256 bytes recommended); workspaces to 256 bytes.
+ * - Blocks of vectors are column-major with leading dimension `ld` >= n,
+ *   counted in elements: column j starts at base + j*ld.
+ * - Small s x s matrices (W, B2, beta) live in device memory, row-major:
+ *   entry (i, j) at i*s + j.
+ * - Every call returns an sspcg_status.  On an argument error nothing is
+ *   enqueued and no output is touched.  HIP failures return SSPCG_ERR_HIP;
+ *   sspcg_last_error() then holds the HIP message (per thread).  No C++
+ *   exception crosses this interface.
+ * - Results are deterministic: every reduction runs in a fixed order, so
+ *   repeated calls with equal inputs give bitwise equal outputs.
+ */
+#ifndef SSPCG_H
+#define SSPCG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SSPCG_ABI_VERSION 1
+#define SSPCG_MAX_S 16          /* largest supported step size s */
+
+typedef void* sspcg_stream;     /* hipStream_t */
+
+typedef enum {
+    SSPCG_OK = 0,
+    SSPCG_NOT_CONVERGED = 1,    /* iteration limit reached; x holds the last iterate */
+    SSPCG_ERR_ARG = -1,         /* invalid argument; nothing was done */
+    SSPCG_ERR_HIP = -2,         /* a HIP runtime call failed */
+    SSPCG_ERR_BREAKDOWN = -3,   /* non-positive Gram or matrix diagonal (A not SPD) */
+    SSPCG_ERR_WORKSPACE = -4,   /* workspace smaller than sspcg_workspace_bytes() */
+    SSPCG_ERR_NONFINITE = -5,   /* NaN or Inf in the data or the iteration */
+    SSPCG_ERR_UNSUPPORTED = -6  /* option not available for this matrix */
+} sspcg_status;
+
+typedef enum {
+    SSPCG_FP64 = 0,             /* everything in binary64 */
+    SSPCG_MIXED = 1             /* FP32 inner solves inside FP64 iterative refinement */
+} sspcg_precision;
+
+typedef enum {
+    SSPCG_GRAM_FGS = 0,         /* `sweeps` FGS sweeps from zero (Sec. 3.1) */
+    SSPCG_GRAM_CHOLESKY = 1     /* exact solve by Cholesky (the paper's comparison) */
+} sspcg_gram_solver;
+
+/* Element type of vector arguments of the kernel-level calls. */
+typedef enum { SSPCG_F64 = 0, SSPCG_F32 = 1 } sspcg_dtype;
+
+/* Flags of sspcg_matrix_create. */
+#define SSPCG_MATRIX_FP32 1     /* also keep FP32 values (needed by SSPCG_MIXED) */
+
+/* Parameters of a solve (the requirements of Algorithm 1 plus the basis
+ * interval of Sec. 2).  Use sspcg_default_params() and change fields. */
+typedef struct {
+    int32_t s;                  /* step size, 1..SSPCG_MAX_S */
+    int32_t sweeps;             /* FGS sweeps nu, 1..1000 */
+    double lambda_min;          /* Chebyshev interval of M^{-1}A, 0 <= lambda_min < lambda_max */
+    double lambda_max;
+    double tol;                 /* stop when ||r|| <= tol ||b|| (recursive r; FP64 true r in MIXED) */
+    int32_t max_outer;          /* outer-iteration limit (FP64) / per inner solve limit (MIXED) */
+    int32_t precision;          /* sspcg_precision */
+    double inner_tol;           /* MIXED: inner solve stops at ||r_in|| <= inner_tol ||r|| */
+    int32_t max_refine;         /* MIXED: limit on FP64 residual corrections */
+    int32_t gram;               /* sspcg_gram_solver */
+    int32_t check_every;        /* outer iterations enqueued between host polls (>= 1) */
+    int32_t profile;            /* 1: time every phase with HIP events (sspcg_last_profile) */
+} sspcg_params;
+
+/* Outcome of a solve (host struct filled by the solve calls). */
+typedef struct {
+    int32_t status;             /* sspcg_status */
+    int32_t outer_iters;        /* x updates taken (FP64) / inner iterations summed (MIXED) */
+    int32_t refinements;        /* MIXED: FP64 corrections applied */
+    int32_t reserved;
+    double relres;              /* ||r|| / ||b|| of the residual the stop test used */
+    double device_ms;           /* GPU time of the solve, from HIP events */
+} sspcg_result;
+
+/* Phases of the s-step solve, as timed by the profile. */
+enum {
+    SSPCG_PHASE_SPMV = 0,       /* matrix powers kernel: s SpMV launches with fused epilogue */
+    SSPCG_PHASE_GRAM_UPDATE,    /* block update fused with the W, b1 reduction */
+    SSPCG_PHASE_GRAM_RECT,      /* B2 = -Q^T AZ reduction */
+    SSPCG_PHASE_FGS,            /* finishing of a reduction + FGS solve (alpha or beta) */
+    SSPCG_PHASE_NORM,           /* residual norm, stop test */
+    SSPCG_PHASE_XR,             /* x, r update with ||r||^2 and z_1 */
+    SSPCG_NUM_PHASES
+};
+
+/* Per-phase GPU time of the last profiled solve on a matrix handle, counted
+ * over the phases that did work (the launches enqueued after the stop test
+ * passed, which return at once, are excluded). */
+typedef struct {
+    int64_t launches[SSPCG_NUM_PHASES];   /* kernel launches that did work */
+    double ms[SSPCG_NUM_PHASES];          /* GPU time between the bracketing events */
+    int64_t outer_iters;                  /* outer iterations covered */
+} sspcg_profile;
+
+typedef struct sspcg_matrix sspcg_matrix;   /* opaque */
+
+/* ---------------------------------------------------------------- misc */
+int sspcg_abi_version(void);
+const char* sspcg_status_string(int status);
+/* Detail of the last failing call on this thread ("" if none). */
+const char* sspcg_last_error(void);
+void sspcg_default_params(sspcg_params* p);
+
+/* ---------------------------------------------------------------- matrix */
+/* Builds the library's copy of a CSR matrix on the current device.
+ *   row_ptr (device, int32[n+1]), col (device, int32[nnz]), val (device,
+ *   double[nnz]): CSR with row_ptr[0] = 0, increasing row pointers, columns in
+ *   [0, n) and every diagonal entry stored.  Column order inside a row fixes
+ *   the summation order of the SpMV.
+ * The library allocates device memory for its sliced layout (64-row slices,
+ * each stored column-major and padded to its longest row), the Jacobi
+ * scaling 1/diag(A) and, with SSPCG_MATRIX_FP32, FP32 copies of both; it
+ * frees them in sspcg_matrix_destroy.  The call synchronizes `stream`.
+ * Solves use only the library's copy, but sspcg_matrix_update_values,
+ * sspcg_csr_value_grad and the diffusion calls read the caller's row_ptr and
+ * col again: keep them alive as long as the handle is used with those calls.
+ * Returns SSPCG_ERR_ARG for a malformed pattern (checked on the device) and
+ * SSPCG_ERR_BREAKDOWN when a diagonal entry is missing or not positive. */
+int sspcg_matrix_create(int32_t n, int32_t nnz, const int32_t* row_ptr, const int32_t* col,
+                        const double* val, int32_t flags, sspcg_stream stream,
+                        sspcg_matrix** out);
+/* Replaces the values (same pattern): val is device double[nnz] in CSR
+ * order.  Synchronizes `stream`; SSPCG_ERR_BREAKDOWN as for create. */
+int sspcg_matrix_update_values(sspcg_matrix* A, const double* val, sspcg_stream stream);
+int sspcg_matrix_destroy(sspcg_matrix* A);
+/* n, nnz, stored slots of the sliced layout (nnz plus padding), device bytes held. */
+int sspcg_matrix_info(const sspcg_matrix* A, int64_t* n, int64_t* nnz, int64_t* slots,
+                      int64_t* device_bytes);
+
+/* ---------------------------------------------------------------- solvers */
+/* Workspace (device bytes) that sspcg_solve / sspcg_pcg_solve need. */
+int sspcg_workspace_bytes(const sspcg_matrix* A, const sspcg_params* p, size_t* bytes);
+
+/* s-step PCG, Algorithm 1 with Algorithm 2 and FGS Gram solves.
+ *   b (device, double[n]); x (device, double[n]): x0 on entry, the solution
+ *   on exit - the iterate at the first passing stop test.
+ *   work (device, >= sspcg_workspace_bytes): scratch, contents undefined after.
+ *   res (host, required), history (host, optional): per outer iteration k,
+ *   3 doubles {relative residual after the x update, eta_alpha, eta_beta}
+ *   (the reduced-system residuals of Sec. 3.4; 0 where not formed), room for
+ *   3*max_outer doubles.  MIXED: per refinement the FP64 true relative
+ *   residual, room for max_refine+1 doubles.
+ * If ||b|| = 0 the result is x = 0 after no iteration; if the starting
+ * residual already passes the test, x is returned unchanged.
+ * On SSPCG_ERR_BREAKDOWN / SSPCG_ERR_NONFINITE, x holds the last iterate
+ * before the failing Gram solve.  Blocks until done. */
+int sspcg_solve(const sspcg_matrix* A, const double* b, double* x, const sspcg_params* p,
+                void* work, size_t work_bytes, sspcg_stream stream, sspcg_result* res,
+                double* history);
+
+/* Profile of the last sspcg_solve on A that ran with p->profile = 1
+ * (zeros if none).  out: host struct. */
+int sspcg_last_profile(const sspcg_matrix* A, sspcg_profile* out);
+
+/* Classical Jacobi PCG (the method s-step PCG replaces), same stop test.
+ * Uses p->tol, p->max_outer (as the iteration limit) and p->check_every.
+ * history (host, optional): relative residual per iteration. */
+int sspcg_pcg_solve(const sspcg_matrix* A, const double* b, double* x, const sspcg_params* p,
+                    void* work, size_t work_bytes, sspcg_stream stream, sspcg_result* res,
+                    double* history);
+
+/* ---------------------------------------------------------------- kernels */
+/* The kernels the solvers are built from, for step-by-step checking.  All
+ * enqueue on `stream` and return at once.  `work` is device scratch of at
+ * least sspcg_kernel_work_bytes(); its contents are undefined afterwards. */
+size_t sspcg_kernel_work_bytes(int32_t s);
+
+/* y = A x (x, y device, dtype elements; F32 needs SSPCG_MATRIX_FP32: values
+ * and x in FP32, products and sum in FP64, one rounding to FP32). */
+int sspcg_spmv(const sspcg_matrix* A, int32_t dtype, const void* x, void* y, sspcg_stream stream);
+
+/* Algorithm 2 for the residual r: Z = [z_1..z_s] and P = [p_1..p_{s+1}]
+ * (device, n x s and n x (s+1), leading dimension ld, dtype elements) with
+ * z_1 = M^{-1} r, z_{q+1} the Chebyshev three-term recurrence in
+ * alpha M^{-1}A - sigma I (first step the T_1 one), p_1 = r, p_{q+1} = A z_q;
+ * alpha = 2/(lmax-lmin), sigma = (lmax+lmin)/(lmax-lmin), gamma = 1. */
+int sspcg_mpk(const sspcg_matrix* A, int32_t dtype, const void* r, int32_t s, double lmin,
+              double lmax, void* Z, void* P, int64_t ld, sspcg_stream stream);
+
+/* Block update fused with the Gram reduction of Algorithm 1:
+ *   if beta != NULL: Q <- Z + Q beta and AQ <- AZ + AQ beta (in place);
+ *   else:            Q <- Z and AQ <- AZ (the first block);
+ * then W = Q^T AQ (lower triangle i >= j computed, mirrored) and b1 = Q^T r.
+ * Q, AQ, Z, AZ: device n x s, ld; r: device n; dtype elements.  beta, W:
+ * device double s*s; b1: device double s.  Gram sums are FP64. */
+int sspcg_block_update_gram(int64_t n, int32_t s, int32_t dtype, const void* Z, void* Q,
+                            const void* AZ, void* AQ, const double* beta, const void* r,
+                            int64_t ld, double* W, double* b1, void* work, size_t work_bytes,
+                            sspcg_stream stream);
+
+/* B2 = -Q^T AZ (all s*s entries; device double, row-major), Algorithm 1's
+ * right-hand side of the beta system.  FP64 sums. */
+int sspcg_gram_rect(int64_t n, int32_t s, int32_t dtype, const void* Q, const void* AZ,
+                    int64_t ld, double* B2, void* work, size_t work_bytes, sspcg_stream stream);
+
+/* FGS (or Cholesky) solve of W X = B for nrhs right-hand sides: B, X device
+ * double s x nrhs row-major, W device double s x s (lower triangle read).
+ * `sweeps` sweeps of (D + L_W) x_new = b - L_W^T x_old from x = 0.
+ * status (device int32): set to SSPCG_ERR_BREAKDOWN for W_ii <= 0 and to
+ * SSPCG_ERR_NONFINITE for NaN/Inf in W or B, else SSPCG_OK. */
+int sspcg_fgs(int32_t s, int32_t nrhs, const double* W, const double* B, int32_t sweeps,
+              int32_t gram_solver, double* X, int32_t* status, sspcg_stream stream);
+
+/* x += Q alpha; r -= AQ alpha; rr = ||r||^2 (device double, FP64 sum);
+ * when z1 != NULL also z1 = M^{-1} r.  alpha: device double s. */
+int sspcg_xr_update(const sspcg_matrix* A, int32_t s, int32_t dtype, const void* Q,
+                    const void* AQ, const double* alpha, int64_t ld, void* x, void* r,
+                    void* z1, double* rr, void* work, size_t work_bytes, sspcg_stream stream);
+
+/* ---------------------------------------------------------- differentiation */
+/* gval_e = -lambda_i x_j for every stored entry e = (i, j) (device double
+ * arrays; gval in CSR order): the gradient of a loss L(x) with respect to the
+ * matrix values when A x = b and A lambda = dL/dx. */
+int sspcg_csr_value_grad(const sspcg_matrix* A, const double* lambda, const double* x,
+                         double* gval, sspcg_stream stream);
+
+/* Values of the 7-point variable-coefficient diffusion operator on the
+ * matrix's pattern: k = exp(theta) per cell, off-diagonal -w_ij with
+ * w_ij = 2 k_i k_j/(k_i + k_j), diagonal sum_j w_ij + (6 - deg_i) k_i.
+ * theta (device double[n]), val (device double[nnz], CSR order). */
+int sspcg_diffusion7_assemble(const sspcg_matrix* A, const double* theta, double* val,
+                              sspcg_stream stream);
+
+/* Vector-Jacobian product of sspcg_diffusion7_assemble:
+ * gtheta_c = sum_e gval_e d(val_e)/d(theta_c) (device double arrays). */
+int sspcg_diffusion7_theta_grad(const sspcg_matrix* A, const double* theta, const double* gval,
+                                double* gtheta, sspcg_stream stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SSPCG_H */

@@ -1,0 +1,282 @@
+// Tall-skinny block kernels of the outer iteration (Algorithm 1): the fused
+// block update + Gram reduction, the right-hand side of the beta system,
+// and the x / r update with the residual norm and the first basis vector.
+//
+// All are row-parallel and stream every input once: thread i owns row i of
+// every column (columns are ld apart, so a wave's load of one column is 512
+// contiguous bytes).  Gram sums are FP64 per thread, then reduced over the
+// block in a fixed order into per-block partials; a single-block kernel
+// finishes them (fgs.hip).  The step size s is a template parameter so the
+// s(s+1)/2 + s accumulators live in registers.
+
+#include "launch.h"
+
+namespace sspcg {
+
+namespace {
+
+template <int S, typename T, bool FIRST>
+__global__ __launch_bounds__(kRowBlock) void k_update_gram(int64_t n, int64_t ld,
+                                                           const T* __restrict__ Z,
+                                                           T* __restrict__ Q,
+                                                           const T* __restrict__ AZ,
+                                                           T* __restrict__ AQ,
+                                                           const double* __restrict__ beta,
+                                                           const T* __restrict__ r,
+                                                           double* __restrict__ partials,
+                                                           const Ctrl* __restrict__ ctrl)
+{
+    if (ctrl && ctrl->done) return;
+    constexpr int K = S * (S + 1) / 2 + S;
+    double acc[K];
+#pragma unroll
+    for (int e = 0; e < K; ++e) acc[e] = 0.0;
+    const int64_t ntiles = (n + kRowBlock - 1) / kRowBlock;
+    const TileRange tr = xcd_tiles(ntiles);
+    for (int64_t t = tr.first; t < tr.end; t += tr.step) {
+        const int64_t i = t * kRowBlock + threadIdx.x;
+        if (i >= n) break;
+        double q[S], aq[S];
+        if (FIRST) {
+#pragma unroll
+            for (int j = 0; j < S; ++j) {
+                const T zj = Z[j * ld + i], azj = AZ[j * ld + i];
+                Q[j * ld + i] = zj;
+                AQ[j * ld + i] = azj;
+                q[j] = (double)zj;
+                aq[j] = (double)azj;
+            }
+        } else {
+            double qo[S], aqo[S];
+#pragma unroll
+            for (int j = 0; j < S; ++j) {
+                qo[j] = (double)Q[j * ld + i];
+                aqo[j] = (double)AQ[j * ld + i];
+            }
+#pragma unroll
+            for (int j = 0; j < S; ++j) {
+                double tq = 0.0, taq = 0.0;
+#pragma unroll
+                for (int l = 0; l < S; ++l) {
+                    tq = fma(qo[l], beta[l * S + j], tq);
+                    taq = fma(aqo[l], beta[l * S + j], taq);
+                }
+                const T qn = (T)((double)Z[j * ld + i] + tq);
+                const T aqn = (T)((double)AZ[j * ld + i] + taq);
+                Q[j * ld + i] = qn;
+                AQ[j * ld + i] = aqn;
+                q[j] = (double)qn;
+                aq[j] = (double)aqn;
+            }
+        }
+        const double ri = (double)r[i];
+        int e = 0;
+#pragma unroll
+        for (int a = 0; a < S; ++a)
+#pragma unroll
+            for (int b = 0; b <= a; ++b) {
+                acc[e] = fma(q[a], aq[b], acc[e]);
+                ++e;
+            }
+#pragma unroll
+        for (int a = 0; a < S; ++a) acc[K - S + a] = fma(q[a], ri, acc[K - S + a]);
+    }
+    block_partials<K, kRowBlock>(acc, partials);
+}
+
+template <int S, typename T>
+__global__ __launch_bounds__(kRowBlock) void k_gram_rect(int64_t n, int64_t ld,
+                                                         const T* __restrict__ Q,
+                                                         const T* __restrict__ AZ,
+                                                         double* __restrict__ partials,
+                                                         const Ctrl* __restrict__ ctrl)
+{
+    if (ctrl && ctrl->done) return;
+    constexpr int K = S * S;
+    double acc[K];
+#pragma unroll
+    for (int e = 0; e < K; ++e) acc[e] = 0.0;
+    const int64_t ntiles = (n + kRowBlock - 1) / kRowBlock;
+    const TileRange tr = xcd_tiles(ntiles);
+    for (int64_t t = tr.first; t < tr.end; t += tr.step) {
+        const int64_t i = t * kRowBlock + threadIdx.x;
+        if (i >= n) break;
+        double q[S], az[S];
+#pragma unroll
+        for (int j = 0; j < S; ++j) {
+            q[j] = (double)Q[j * ld + i];
+            az[j] = (double)AZ[j * ld + i];
+        }
+#pragma unroll
+        for (int a = 0; a < S; ++a)
+#pragma unroll
+            for (int b = 0; b < S; ++b) acc[a * S + b] = fma(q[a], az[b], acc[a * S + b]);
+    }
+    block_partials<K, kRowBlock>(acc, partials);
+}
+
+template <int S, typename T>
+__global__ __launch_bounds__(kRowBlock) void k_xr(int64_t n, int64_t ld, const T* __restrict__ Q,
+                                                  const T* __restrict__ AQ,
+                                                  const double* __restrict__ alpha,
+                                                  T* __restrict__ x, T* __restrict__ r,
+                                                  const T* __restrict__ dinv, T* __restrict__ z1,
+                                                  double* __restrict__ partials,
+                                                  const Ctrl* __restrict__ ctrl)
+{
+    if (ctrl && ctrl->done) return;
+    double al[S];
+#pragma unroll
+    for (int j = 0; j < S; ++j) al[j] = alpha[j];
+    double acc[1] = {0.0};
+    const int64_t ntiles = (n + kRowBlock - 1) / kRowBlock;
+    const TileRange tr = xcd_tiles(ntiles);
+    for (int64_t t = tr.first; t < tr.end; t += tr.step) {
+        const int64_t i = t * kRowBlock + threadIdx.x;
+        if (i >= n) break;
+        double qa = 0.0, aqa = 0.0;
+#pragma unroll
+        for (int j = 0; j < S; ++j) {
+            qa = fma((double)Q[j * ld + i], al[j], qa);
+            aqa = fma((double)AQ[j * ld + i], al[j], aqa);
+        }
+        x[i] = (T)((double)x[i] + qa);
+        const T ri = (T)((double)r[i] - aqa);
+        r[i] = ri;
+        if (z1) z1[i] = (T)((double)dinv[i] * (double)ri);
+        acc[0] = fma((double)ri, (double)ri, acc[0]);
+    }
+    block_partials<1, kRowBlock>(acc, partials);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kRowBlock) void k_axpy_up(int64_t n, double* __restrict__ x,
+                                                       const T* __restrict__ d,
+                                                       const Ctrl* __restrict__ ctrl)
+{
+    if (ctrl && ctrl->done) return;
+    const int64_t stride = (int64_t)gridDim.x * kRowBlock;
+    for (int64_t i = (int64_t)blockIdx.x * kRowBlock + threadIdx.x; i < n; i += stride)
+        x[i] += (double)d[i];
+}
+
+template <typename T>
+__global__ __launch_bounds__(kRowBlock) void k_fill(int64_t n, T* __restrict__ x, T v)
+{
+    const int64_t stride = (int64_t)gridDim.x * kRowBlock;
+    for (int64_t i = (int64_t)blockIdx.x * kRowBlock + threadIdx.x; i < n; i += stride) x[i] = v;
+}
+
+}  // namespace
+
+int row_grid(int64_t n)
+{
+    return persistent_grid((n + kRowBlock - 1) / kRowBlock, 4);
+}
+
+#define SSPCG_S_CASES(X) \
+    X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16)
+
+template <typename T>
+int launch_update_gram(int64_t n, int s, const T* Z, T* Q, const T* AZ, T* AQ, const double* beta,
+                       const T* r, int64_t ld, double* partials, int* G_out, const Ctrl* ctrl,
+                       hipStream_t st)
+{
+    const int G = row_grid(n);
+    switch (s) {
+#define X(S)                                                                                     \
+    case S:                                                                                      \
+        if (beta)                                                                                \
+            hipLaunchKernelGGL((k_update_gram<S, T, false>), dim3(G), dim3(kRowBlock), 0, st, n, \
+                               ld, Z, Q, AZ, AQ, beta, r, partials, ctrl);                       \
+        else                                                                                     \
+            hipLaunchKernelGGL((k_update_gram<S, T, true>), dim3(G), dim3(kRowBlock), 0, st, n,  \
+                               ld, Z, Q, AZ, AQ, beta, r, partials, ctrl);                       \
+        break;
+        SSPCG_S_CASES(X)
+#undef X
+    default:
+        set_error("s out of range");
+        return SSPCG_ERR_ARG;
+    }
+    SSPCG_LAUNCHED("k_update_gram");
+    *G_out = G;
+    return SSPCG_OK;
+}
+
+template <typename T>
+int launch_gram_rect(int64_t n, int s, const T* Q, const T* AZ, int64_t ld, double* partials,
+                     int* G_out, const Ctrl* ctrl, hipStream_t st)
+{
+    const int G = row_grid(n);
+    switch (s) {
+#define X(S)                                                                                    \
+    case S:                                                                                     \
+        hipLaunchKernelGGL((k_gram_rect<S, T>), dim3(G), dim3(kRowBlock), 0, st, n, ld, Q, AZ, \
+                           partials, ctrl);                                                     \
+        break;
+        SSPCG_S_CASES(X)
+#undef X
+    default:
+        set_error("s out of range");
+        return SSPCG_ERR_ARG;
+    }
+    SSPCG_LAUNCHED("k_gram_rect");
+    *G_out = G;
+    return SSPCG_OK;
+}
+
+template <typename T>
+int launch_xr(int64_t n, int s, const T* Q, const T* AQ, const double* alpha, int64_t ld, T* x,
+              T* r, const T* dinv, T* z1, double* partials, int* G_out, const Ctrl* ctrl,
+              hipStream_t st)
+{
+    const int G = row_grid(n);
+    switch (s) {
+#define X(S)                                                                                   \
+    case S:                                                                                    \
+        hipLaunchKernelGGL((k_xr<S, T>), dim3(G), dim3(kRowBlock), 0, st, n, ld, Q, AQ, alpha, \
+                           x, r, dinv, z1, partials, ctrl);                                    \
+        break;
+        SSPCG_S_CASES(X)
+#undef X
+    default:
+        set_error("s out of range");
+        return SSPCG_ERR_ARG;
+    }
+    SSPCG_LAUNCHED("k_xr");
+    *G_out = G;
+    return SSPCG_OK;
+}
+
+template <typename T>
+int launch_axpy_up(int64_t n, double* x, const T* d, const Ctrl* ctrl, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_axpy_up<T>), dim3(row_grid(n)), dim3(kRowBlock), 0, st, n, x, d, ctrl);
+    SSPCG_LAUNCHED("k_axpy_up");
+    return SSPCG_OK;
+}
+
+template <typename T>
+int launch_fill(int64_t n, T* x, T v, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_fill<T>), dim3(row_grid(n)), dim3(kRowBlock), 0, st, n, x, v);
+    SSPCG_LAUNCHED("k_fill");
+    return SSPCG_OK;
+}
+
+#define SSPCG_INST(T)                                                                            \
+    template int launch_update_gram<T>(int64_t, int, const T*, T*, const T*, T*, const double*, \
+                                       const T*, int64_t, double*, int*, const Ctrl*,           \
+                                       hipStream_t);                                             \
+    template int launch_gram_rect<T>(int64_t, int, const T*, const T*, int64_t, double*, int*,  \
+                                     const Ctrl*, hipStream_t);                                  \
+    template int launch_xr<T>(int64_t, int, const T*, const T*, const double*, int64_t, T*, T*, \
+                              const T*, T*, double*, int*, const Ctrl*, hipStream_t);           \
+    template int launch_axpy_up<T>(int64_t, double*, const T*, const Ctrl*, hipStream_t);       \
+    template int launch_fill<T>(int64_t, T*, T, hipStream_t);
+SSPCG_INST(double)
+SSPCG_INST(float)
+#undef SSPCG_INST
+
+}  // namespace sspcg

@@ -1,0 +1,127 @@
+// Internal declarations shared by the HIP sources of libsspcg.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "sspcg.h"
+
+namespace sspcg {
+
+constexpr int kWave = 64;          // CDNA wavefront width
+constexpr int kSlice = 64;         // rows per slice of the sliced layout (one per lane)
+constexpr int kRowBlock = 256;     // threads of the row-parallel kernels
+constexpr int kFinBlock = 1024;    // threads of the single-block finishing kernels
+constexpr int kNumXcd = 8;         // accelerator complex dies of an MI355X
+constexpr int kMaxGrid = 4096;     // upper bound on blocks of persistent kernels
+constexpr int kMaxPartials = SSPCG_MAX_S * SSPCG_MAX_S + SSPCG_MAX_S;  // values per block
+
+// Device-side control block of a running solve.  Kernels of the outer loop
+// read `done` on entry and return at once when it is set, so the host can
+// enqueue iterations ahead of the convergence test.
+struct Ctrl {
+    int32_t done;       // 1 once the solve has ended
+    int32_t status;     // sspcg_status when done
+    int32_t iter;       // x updates taken
+    int32_t max_iter;   // limit on x updates
+    double nb;          // reference norm of the relative residual
+    double tol;         // stop when ||r|| <= tol * nb
+    double relres;      // last relative residual
+    double rho[2];      // classical PCG: r^T z, double-buffered by iteration parity
+    double sums[4];     // results of the setup reductions
+    double pad[5];
+};
+static_assert(sizeof(Ctrl) == 128, "Ctrl layout");
+
+// Sliced layout of a CSR matrix: slice c holds rows 64c..64c+63; entry k of
+// lane l sits at slice_ptr[c] + 64k + l; each slice is padded to its
+// longest row with value 0 and column = the row itself.
+template <typename T>
+struct Sell {
+    int32_t n;
+    int64_t nslices;
+    const int64_t* slice_ptr;   // nslices + 1 offsets, multiples of 64
+    const int32_t* col;
+    const T* val;
+    const T* dinv;              // 1 / diag(A)
+};
+
+// Grid of a persistent row kernel: a multiple of kNumXcd blocks.
+int persistent_grid(int64_t ntiles, int blocks_per_cu);
+int num_cus();
+
+// Error plumbing for the C ABI.
+void set_error(const std::string& msg);
+int hip_fail(hipError_t e, const char* what);
+#define SSPCG_HIP(call)                                        \
+    do {                                                       \
+        hipError_t e_ = (call);                                \
+        if (e_ != hipSuccess) return ::sspcg::hip_fail(e_, #call); \
+    } while (0)
+#define SSPCG_LAUNCHED(what)                                   \
+    do {                                                       \
+        hipError_t e_ = hipGetLastError();                     \
+        if (e_ != hipSuccess) return ::sspcg::hip_fail(e_, what); \
+    } while (0)
+
+// ------------------------------------------------------------------ device
+
+// Workgroups are dispatched to the dies round-robin (block b runs on die
+// b % 8), and each die has its own L2.  Give every die a contiguous range of
+// tiles so that the neighbours a stencil row gathers stay in that die's L2.
+struct TileRange {
+    int64_t first, end, step;
+};
+
+__device__ inline TileRange xcd_tiles(int64_t ntiles)
+{
+    const int G = gridDim.x, b = blockIdx.x;
+    if (G >= kNumXcd && G % kNumXcd == 0) {
+        const int x = b % kNumXcd, j = b / kNumXcd, per = G / kNumXcd;
+        const int64_t lo = ntiles * x / kNumXcd, hi = ntiles * (x + 1) / kNumXcd;
+        return {lo + j, hi, per};
+    }
+    return {b, ntiles, G};
+}
+
+__device__ inline double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+// Reduces K per-thread accumulators over the block in a fixed order and
+// writes the block's partial sums to partials[k * G + blockIdx.x].
+template <int K, int NT>
+__device__ inline void block_partials(double (&acc)[K], double* __restrict__ partials)
+{
+    __shared__ double sm[NT / kWave][K > 0 ? K : 1];
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const double v = wave_sum(acc[k]);
+        if (lane == 0) sm[wave][k] = v;
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < K; k += NT) {
+        double s = 0.0;
+#pragma unroll
+        for (int w = 0; w < NT / kWave; ++w) s += sm[w][k];
+        partials[(int64_t)k * gridDim.x + blockIdx.x] = s;
+    }
+}
+
+// Sum of partials[e * G + 0 .. G-1] by one wavefront in a fixed order.
+__device__ inline double wave_finish(const double* __restrict__ partials, int e, int G)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    double s = 0.0;
+    for (int g = lane; g < G; g += kWave) s += partials[(int64_t)e * G + g];
+    return wave_sum(s);
+}
+
+}  // namespace sspcg

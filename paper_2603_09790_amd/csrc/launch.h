@@ -1,0 +1,105 @@
+// Host-side launchers of the kernels, shared by the HIP sources.
+#pragma once
+
+#include <vector>
+
+#include "common.h"
+
+struct sspcg_matrix {
+    int32_t n = 0, nnz = 0, flags = 0, device = 0;
+    const int32_t* row_ptr = nullptr;   // caller's CSR (device, not owned)
+    const int32_t* col = nullptr;
+    int64_t nslices = 0, slots = 0;
+    int64_t* slice_ptr = nullptr;       // owned (inside `mem`)
+    int32_t* scol = nullptr;
+    double* sval = nullptr;
+    float* sval32 = nullptr;
+    double* dinv = nullptr;
+    float* dinv32 = nullptr;
+    int32_t* dflags = nullptr;
+    void* mem = nullptr;                // device allocation: slice_ptr, dinv, dinv32, dflags
+    void* mem_vals = nullptr;           // device allocation: scol, sval, sval32
+    size_t mem_bytes = 0;
+    sspcg::Ctrl* host_ctrl = nullptr;   // pinned mirror for polling (2 entries)
+    sspcg_profile profile{};            // last profiled solve
+};
+
+namespace sspcg {
+
+template <typename T>
+Sell<T> sell_view(const sspcg_matrix* A);
+
+// Matrix layout (sell.hip).  inspect validates the CSR input on the device,
+// writes dinv and returns the slice offsets; fill writes the sliced arrays.
+int matrix_inspect(sspcg_matrix* A, const double* val, bool values_only,
+                   std::vector<int64_t>* slice_ptr, hipStream_t st);
+int matrix_fill(sspcg_matrix* A, const double* val, bool values_only, hipStream_t st);
+template <typename T>
+int launch_mpk_start(int64_t n, const T* r, const T* dinv, T* z1, T* p1, hipStream_t st);
+
+// SpMV with the MPK epilogue (sell.hip).
+//   mode 0: y = A x
+//   mode 1: y = A x;  znext = c1 * dinv .* y - c2 * x
+//   mode 2: y = A x;  znext = c1 * dinv .* y - c2 * x - c3 * zprev
+template <typename T>
+int launch_spmv(const sspcg_matrix* A, int mode, const T* x, T* y, const T* zprev, T* znext,
+                double c1, double c2, double c3, const Ctrl* ctrl, hipStream_t st);
+
+// FP64 residual: r = b - A x stored as TR; z1 = dinv_T .* r when z1 != null;
+// partials of {||b - Ax||^2 (FP64), ||r_stored||^2, ||b||^2, r_stored^T z1}.
+template <typename TR>
+int launch_residual(const sspcg_matrix* A, const double* x, const double* b, TR* r, TR* z1,
+                    double* partials, int* G_out, hipStream_t st);
+
+// Classical PCG: q = A p with partials of p^T q.
+int launch_pcg_spmv(const sspcg_matrix* A, const double* p, double* q, double* partials,
+                    int* G_out, const Ctrl* ctrl, hipStream_t st);
+int launch_pcg_update(const sspcg_matrix* A, int64_t k, double* x, double* r, double* z,
+                      const double* p, const double* q, const double* pq_partials, int Gpq,
+                      double* partials, int* G_out, Ctrl* ctrl, hipStream_t st);
+int launch_pcg_pupdate(int64_t n, int64_t k, const double* z, double* p, const double* partials,
+                       int G, Ctrl* ctrl, double* hist, hipStream_t st);
+
+// Block kernels (block.hip).
+int row_grid(int64_t n);
+template <typename T>
+int launch_update_gram(int64_t n, int s, const T* Z, T* Q, const T* AZ, T* AQ,
+                       const double* beta, const T* r, int64_t ld, double* partials,
+                       int* G_out, const Ctrl* ctrl, hipStream_t st);
+template <typename T>
+int launch_gram_rect(int64_t n, int s, const T* Q, const T* AZ, int64_t ld, double* partials,
+                     int* G_out, const Ctrl* ctrl, hipStream_t st);
+template <typename T>
+int launch_xr(int64_t n, int s, const T* Q, const T* AQ, const double* alpha, int64_t ld,
+              T* x, T* r, const T* dinv, T* z1, double* partials, int* G_out,
+              const Ctrl* ctrl, hipStream_t st);
+template <typename T>
+int launch_axpy_up(int64_t n, double* x, const T* d, const Ctrl* ctrl, hipStream_t st);
+template <typename T>
+int launch_fill(int64_t n, T* x, T v, hipStream_t st);
+
+// Small kernels (fgs.hip).
+//   which = 0: alpha system (partials hold W lower + b1; W is also stored)
+//   which = 1: beta system (partials hold Q^T AZ; W from Wbuf)
+int launch_fgs_step(int s, int which, const double* partials, int G, double* Wbuf, double* out,
+                    int sweeps, int solver, Ctrl* ctrl, double* hist, hipStream_t st);
+int launch_fgs_direct(int s, int nrhs, const double* W, const double* B, int sweeps, int solver,
+                      double* X, int32_t* status, hipStream_t st);
+// Finishes ||r||^2 for outer iteration k: relres, stop test, history.
+int launch_norm_step(const double* partials, int G, int64_t k, Ctrl* ctrl, double* hist,
+                     hipStream_t st);
+// Finishes K partial sums into out[0..K).
+int launch_finish(const double* partials, int K, int G, double* out, hipStream_t st);
+// Kernel-level Gram output: W (mirrored) and b1, or B2 = -sums.
+int launch_gram_out(int s, int which, const double* partials, int G, double* W, double* b1,
+                    hipStream_t st);
+
+// Differentiation (diff.hip).
+int launch_value_grad(const sspcg_matrix* A, const double* lambda, const double* x,
+                      double* gval, hipStream_t st);
+int launch_diffusion7_assemble(const sspcg_matrix* A, const double* theta, double* val,
+                               hipStream_t st);
+int launch_diffusion7_theta_grad(const sspcg_matrix* A, const double* theta, const double* gval,
+                                 double* gtheta, hipStream_t st);
+
+}  // namespace sspcg

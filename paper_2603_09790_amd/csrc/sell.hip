@@ -1,0 +1,529 @@
+// Sliced layout of the CSR matrix and the kernels that stream it: SpMV with
+// the fused matrix-powers epilogue (Algorithm 2), the FP64 residual, and the
+// SpMV of classical PCG.
+//
+// Layout.  Slice c holds rows 64c..64c+63, one per lane of a wavefront.
+// Entry k of every row in the slice is stored contiguously (64 values, then
+// 64 column indices), so each load instruction of the wave reads 512 bytes
+// of values and 256 bytes of indices with no gaps.  A slice is padded to its
+// longest row; a padding slot has value 0 and the row itself as column, so
+// it adds an exact zero and gathers a value the row needs anyway.  For the
+// 27-point stencil on 192^3 the padding is 0.4% of the nonzeros.  The
+// entries of a row keep their CSR order, which is the summation order.
+
+#include <algorithm>
+#include <vector>
+
+#include "launch.h"
+
+namespace sspcg {
+
+namespace {
+
+constexpr int kFlagPattern = 1, kFlagDiag = 2, kFlagValue = 4;
+
+__global__ __launch_bounds__(kRowBlock) void k_inspect(int32_t n, int32_t nnz, int64_t nslices,
+                                                       const int32_t* __restrict__ rp,
+                                                       const int32_t* __restrict__ col,
+                                                       const double* __restrict__ val,
+                                                       int32_t* __restrict__ flags,
+                                                       int32_t* __restrict__ width,
+                                                       double* __restrict__ dinv,
+                                                       float* __restrict__ dinv32,
+                                                       bool values_only)
+{
+    const int64_t i = (int64_t)blockIdx.x * kRowBlock + threadIdx.x;
+    int len = 0;
+    if (i < n) {
+        const int32_t a = rp[i], b = rp[i + 1];
+        int f = 0;
+        if (i == 0 && a != 0) f |= kFlagPattern;
+        if (i == n - 1 && b != nnz) f |= kFlagPattern;
+        if (a < 0 || b < a || b > nnz) {
+            f |= kFlagPattern;
+        } else {
+            len = b - a;
+            double d = 0.0;
+            bool has = false;
+            for (int32_t e = a; e < b; ++e) {
+                const int32_t c = col[e];
+                const double v = val[e];
+                if (!values_only && (c < 0 || c >= n)) f |= kFlagPattern;
+                if (!isfinite(v)) f |= kFlagValue;
+                if (c == i) {
+                    d = v;
+                    has = true;
+                }
+            }
+            if (!has || !(d > 0.0)) f |= kFlagDiag;
+            const double di = (has && d > 0.0) ? 1.0 / d : 0.0;
+            dinv[i] = di;
+            if (dinv32) dinv32[i] = (float)di;
+        }
+        if (f) atomicOr(flags, f);
+    }
+    int w = len;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) w = max(w, __shfl_xor(w, off, kWave));
+    if ((threadIdx.x & (kWave - 1)) == 0) {
+        const int64_t c = i / kSlice;
+        if (c < nslices) width[c] = w;
+    }
+}
+
+__global__ __launch_bounds__(kRowBlock) void k_fill(int32_t n, int64_t nslices,
+                                                    const int32_t* __restrict__ rp,
+                                                    const int32_t* __restrict__ col,
+                                                    const double* __restrict__ val,
+                                                    const int64_t* __restrict__ slice_ptr,
+                                                    int32_t* __restrict__ scol,
+                                                    double* __restrict__ sval,
+                                                    float* __restrict__ sval32, bool values_only)
+{
+    const int64_t i = (int64_t)blockIdx.x * kRowBlock + threadIdx.x;
+    const int64_t c = i / kSlice;
+    if (c >= nslices) return;
+    const int lane = (int)(i % kSlice);
+    const int64_t base = slice_ptr[c];
+    const int w = (int)((slice_ptr[c + 1] - base) / kSlice);
+    int32_t a = 0, len = 0;
+    if (i < n) {
+        a = rp[i];
+        len = rp[i + 1] - a;
+    }
+    for (int k = 0; k < w; ++k) {
+        const int64_t slot = base + (int64_t)k * kSlice + lane;
+        double v = 0.0;
+        int32_t cc = i < n ? (int32_t)i : 0;
+        if (k < len) {
+            v = val[a + k];
+            cc = col[a + k];
+        }
+        sval[slot] = v;
+        if (sval32) sval32[slot] = (float)v;
+        if (!values_only) scol[slot] = cc;
+    }
+}
+
+// ------------------------------------------------------------------ SpMV
+
+template <typename T>
+__device__ inline T ld_stream(const T* p)
+{
+    return __builtin_nontemporal_load(p);
+}
+
+// Sum of one row of the sliced layout, entries in CSR order.  FP32 values
+// and vectors are multiplied exactly in FP64 and summed in FP64.
+template <typename T, int U>
+__device__ inline double sell_row(const int32_t* __restrict__ cp, const T* __restrict__ vp, int w,
+                                  const T* __restrict__ x)
+{
+    double acc = 0.0;
+    int k = 0;
+    for (; k + U <= w; k += U) {
+        int32_t cc[U];
+        T vv[U], xx[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) cc[u] = ld_stream(cp + (int64_t)(k + u) * kSlice);
+#pragma unroll
+        for (int u = 0; u < U; ++u) vv[u] = ld_stream(vp + (int64_t)(k + u) * kSlice);
+#pragma unroll
+        for (int u = 0; u < U; ++u) xx[u] = x[cc[u]];
+#pragma unroll
+        for (int u = 0; u < U; ++u) acc = fma((double)vv[u], (double)xx[u], acc);
+    }
+    for (; k < w; ++k) {
+        const int32_t cc = ld_stream(cp + (int64_t)k * kSlice);
+        const T vv = ld_stream(vp + (int64_t)k * kSlice);
+        acc = fma((double)vv, (double)x[cc], acc);
+    }
+    return acc;
+}
+
+constexpr int kUnroll = 9;
+
+template <typename T, int MODE>
+__global__ __launch_bounds__(kRowBlock) void k_spmv(Sell<T> A, const T* __restrict__ x,
+                                                    T* __restrict__ y,
+                                                    const T* __restrict__ zprev,
+                                                    T* __restrict__ znext, double c1, double c2,
+                                                    double c3, const Ctrl* __restrict__ ctrl)
+{
+    if (ctrl && ctrl->done) return;
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    constexpr int kSlicesPerTile = kRowBlock / kSlice;
+    const int64_t ntiles = (A.nslices + kSlicesPerTile - 1) / kSlicesPerTile;
+    const TileRange tr = xcd_tiles(ntiles);
+    for (int64_t t = tr.first; t < tr.end; t += tr.step) {
+        const int64_t c = t * kSlicesPerTile + wave;
+        if (c >= A.nslices) break;
+        const int64_t base = A.slice_ptr[c];
+        const int w = (int)((A.slice_ptr[c + 1] - base) / kSlice);
+        const double acc = sell_row<T, kUnroll>(A.col + base + lane, A.val + base + lane, w, x);
+        const int64_t row = c * kSlice + lane;
+        if (row < A.n) {
+            const T p = (T)acc;
+            y[row] = p;
+            if (MODE >= 1) {
+                const double t1 = (double)A.dinv[row] * (double)p;
+                double z = c1 * t1 - c2 * (double)x[row];
+                if (MODE == 2) z -= c3 * (double)zprev[row];
+                znext[row] = (T)z;
+            }
+        }
+    }
+}
+
+template <typename TR>
+__global__ __launch_bounds__(kRowBlock) void k_residual(Sell<double> A, const double* __restrict__ x,
+                                                        const double* __restrict__ b,
+                                                        TR* __restrict__ r, TR* __restrict__ z1,
+                                                        const TR* __restrict__ dinvT,
+                                                        double* __restrict__ partials)
+{
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    constexpr int kSlicesPerTile = kRowBlock / kSlice;
+    const int64_t ntiles = (A.nslices + kSlicesPerTile - 1) / kSlicesPerTile;
+    const TileRange tr = xcd_tiles(ntiles);
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t t = tr.first; t < tr.end; t += tr.step) {
+        const int64_t c = t * kSlicesPerTile + wave;
+        if (c >= A.nslices) break;
+        const int64_t base = A.slice_ptr[c];
+        const int w = (int)((A.slice_ptr[c + 1] - base) / kSlice);
+        const double ax = sell_row<double, kUnroll>(A.col + base + lane, A.val + base + lane, w, x);
+        const int64_t row = c * kSlice + lane;
+        if (row < A.n) {
+            const double bi = b[row];
+            const double ri = bi - ax;
+            const TR rs = (TR)ri;
+            r[row] = rs;
+            acc[0] = fma(ri, ri, acc[0]);
+            acc[1] = fma((double)rs, (double)rs, acc[1]);
+            acc[2] = fma(bi, bi, acc[2]);
+            if (z1) {
+                const TR zs = (TR)((double)dinvT[row] * (double)rs);
+                z1[row] = zs;
+                acc[3] = fma((double)rs, (double)zs, acc[3]);
+            }
+        }
+    }
+    block_partials<4, kRowBlock>(acc, partials);
+}
+
+__global__ __launch_bounds__(kRowBlock) void k_pcg_spmv(Sell<double> A, const double* __restrict__ p,
+                                                        double* __restrict__ q,
+                                                        double* __restrict__ partials,
+                                                        const Ctrl* __restrict__ ctrl)
+{
+    if (ctrl->done) return;
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    constexpr int kSlicesPerTile = kRowBlock / kSlice;
+    const int64_t ntiles = (A.nslices + kSlicesPerTile - 1) / kSlicesPerTile;
+    const TileRange tr = xcd_tiles(ntiles);
+    double acc[1] = {0.0};
+    for (int64_t t = tr.first; t < tr.end; t += tr.step) {
+        const int64_t c = t * kSlicesPerTile + wave;
+        if (c >= A.nslices) break;
+        const int64_t base = A.slice_ptr[c];
+        const int w = (int)((A.slice_ptr[c + 1] - base) / kSlice);
+        const double ap = sell_row<double, kUnroll>(A.col + base + lane, A.val + base + lane, w, p);
+        const int64_t row = c * kSlice + lane;
+        if (row < A.n) {
+            q[row] = ap;
+            acc[0] = fma(p[row], ap, acc[0]);
+        }
+    }
+    block_partials<1, kRowBlock>(acc, partials);
+}
+
+// Classical PCG update, iteration k: alpha = rho_k / p^T q (every block sums
+// the same partials in the same order); x += alpha p; r -= alpha q;
+// z = dinv .* r; partials of r^T z and r^T r.
+__global__ __launch_bounds__(kRowBlock) void k_pcg_update(int64_t n, int64_t k, double* __restrict__ x,
+                                                          double* __restrict__ r,
+                                                          double* __restrict__ z,
+                                                          const double* __restrict__ p,
+                                                          const double* __restrict__ q,
+                                                          const double* __restrict__ dinv,
+                                                          const double* __restrict__ pq_part,
+                                                          int Gpq, double* __restrict__ partials,
+                                                          const Ctrl* __restrict__ ctrl)
+{
+    if (ctrl->done) return;
+    __shared__ double s_alpha;
+    if (threadIdx.x < kWave) {
+        const double pq = wave_finish(pq_part, 0, Gpq);
+        if (threadIdx.x == 0) s_alpha = ctrl->rho[k & 1] / pq;
+    }
+    __syncthreads();
+    const double a = s_alpha;
+    double acc[2] = {0.0, 0.0};
+    const int64_t ntiles = (n + kRowBlock - 1) / kRowBlock;
+    const TileRange tr = xcd_tiles(ntiles);
+    for (int64_t t = tr.first; t < tr.end; t += tr.step) {
+        const int64_t i = t * kRowBlock + threadIdx.x;
+        if (i < n) {
+            x[i] = fma(a, p[i], x[i]);
+            const double ri = fma(-a, q[i], r[i]);
+            r[i] = ri;
+            const double zi = dinv[i] * ri;
+            z[i] = zi;
+            acc[0] = fma(ri, zi, acc[0]);
+            acc[1] = fma(ri, ri, acc[1]);
+        }
+    }
+    block_partials<2, kRowBlock>(acc, partials);
+}
+
+// p = z + (rho_{k+1} / rho_k) p, after the stop test of iteration k.  Every
+// block finishes the same partial sums; block 0 records the bookkeeping.
+__global__ __launch_bounds__(kRowBlock) void k_pcg_pupdate(int64_t n, int64_t k,
+                                                           const double* __restrict__ z,
+                                                           double* __restrict__ p,
+                                                           const double* __restrict__ partials,
+                                                           int G, Ctrl* __restrict__ ctrl,
+                                                           double* __restrict__ hist)
+{
+    if (ctrl->done) return;
+    __shared__ double s_v[2];
+    if (threadIdx.x < 2 * kWave) {
+        const int e = threadIdx.x / kWave;
+        const double v = wave_finish(partials, e, G);
+        if ((threadIdx.x & (kWave - 1)) == 0) s_v[e] = v;
+    }
+    __syncthreads();
+    const double rz = s_v[0], rr = s_v[1];
+    const double relres = sqrt(rr) / ctrl->nb;
+    const bool stop = !isfinite(relres) || relres <= ctrl->tol || k + 1 >= ctrl->max_iter;
+    // Block 0 writes only fields no block reads in this launch: rho of the
+    // other parity, relres, iter, status and done (read at entry only, by
+    // blocks that then have nothing left to do once it is set).
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (hist) hist[k] = relres;
+        ctrl->rho[(k + 1) & 1] = rz;
+        ctrl->relres = relres;
+        ctrl->iter = (int32_t)(k + 1);
+        if (!isfinite(relres)) {
+            ctrl->status = SSPCG_ERR_NONFINITE;
+            ctrl->done = 1;
+        } else if (relres <= ctrl->tol) {
+            ctrl->status = SSPCG_OK;
+            ctrl->done = 1;
+        } else if (k + 1 >= ctrl->max_iter) {
+            ctrl->status = SSPCG_NOT_CONVERGED;
+            ctrl->done = 1;
+        }
+    }
+    if (stop) return;
+    const double bt = rz / ctrl->rho[k & 1];
+    const int64_t ntiles = (n + kRowBlock - 1) / kRowBlock;
+    const TileRange tr = xcd_tiles(ntiles);
+    for (int64_t t = tr.first; t < tr.end; t += tr.step) {
+        const int64_t i = t * kRowBlock + threadIdx.x;
+        if (i < n) p[i] = fma(bt, p[i], z[i]);
+    }
+}
+
+// z_1 = M^{-1} r and p_1 = r: the start of the matrix powers kernel.
+template <typename T>
+__global__ __launch_bounds__(kRowBlock) void k_mpk_start(int64_t n, const T* __restrict__ r,
+                                                         const T* __restrict__ dinv,
+                                                         T* __restrict__ z1, T* __restrict__ p1)
+{
+    const int64_t stride = (int64_t)gridDim.x * kRowBlock;
+    for (int64_t i = (int64_t)blockIdx.x * kRowBlock + threadIdx.x; i < n; i += stride) {
+        const T ri = r[i];
+        p1[i] = ri;
+        z1[i] = (T)((double)dinv[i] * (double)ri);
+    }
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ host
+
+int num_cus()
+{
+    static int cus = 0;
+    if (cus == 0) {
+        int dev = 0;
+        hipDeviceProp_t prop;
+        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+            cus = prop.multiProcessorCount;
+        if (cus <= 0) cus = 256;
+    }
+    return cus;
+}
+
+int persistent_grid(int64_t ntiles, int blocks_per_cu)
+{
+    int64_t g = (int64_t)num_cus() * blocks_per_cu;
+    g = std::min<int64_t>(g, kMaxGrid);
+    g = std::min<int64_t>(g, std::max<int64_t>(ntiles, 1));
+    if (g >= kNumXcd) g -= g % kNumXcd;
+    return (int)std::max<int64_t>(g, 1);
+}
+
+template <typename T>
+Sell<T> sell_view(const sspcg_matrix* A);
+
+template <>
+Sell<double> sell_view<double>(const sspcg_matrix* A)
+{
+    return {A->n, A->nslices, A->slice_ptr, A->scol, A->sval, A->dinv};
+}
+
+template <>
+Sell<float> sell_view<float>(const sspcg_matrix* A)
+{
+    return {A->n, A->nslices, A->slice_ptr, A->scol, A->sval32, A->dinv32};
+}
+
+static int spmv_grid(const sspcg_matrix* A)
+{
+    const int64_t ntiles = (A->nslices + kRowBlock / kSlice - 1) / (kRowBlock / kSlice);
+    return persistent_grid(ntiles, 8);
+}
+
+int matrix_inspect(sspcg_matrix* A, const double* val, bool values_only,
+                   std::vector<int64_t>* slice_ptr, hipStream_t st)
+{
+    const int64_t nrows_padded = A->nslices * kSlice;
+    const int blocks = (int)((nrows_padded + kRowBlock - 1) / kRowBlock);
+    std::vector<int32_t> width(A->nslices);
+    int32_t* dwidth = nullptr;
+    SSPCG_HIP(hipMallocAsync((void**)&dwidth, sizeof(int32_t) * A->nslices, st));
+    SSPCG_HIP(hipMemsetAsync(A->dflags, 0, sizeof(int32_t), st));
+    hipLaunchKernelGGL(k_inspect, dim3(blocks), dim3(kRowBlock), 0, st, A->n, A->nnz, A->nslices,
+                       A->row_ptr, A->col, val, A->dflags, dwidth, A->dinv, A->dinv32, values_only);
+    SSPCG_LAUNCHED("k_inspect");
+    int32_t hflags = 0;
+    SSPCG_HIP(hipMemcpyAsync(&hflags, A->dflags, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    SSPCG_HIP(hipMemcpyAsync(width.data(), dwidth, sizeof(int32_t) * A->nslices,
+                             hipMemcpyDeviceToHost, st));
+    SSPCG_HIP(hipFreeAsync(dwidth, st));
+    SSPCG_HIP(hipStreamSynchronize(st));
+    if (hflags & kFlagPattern) {
+        set_error("malformed CSR pattern (row pointers or column indices)");
+        return SSPCG_ERR_ARG;
+    }
+    if (hflags & kFlagValue) {
+        set_error("non-finite matrix value");
+        return SSPCG_ERR_NONFINITE;
+    }
+    if (hflags & kFlagDiag) {
+        set_error("a diagonal entry is missing or not positive: A is not SPD");
+        return SSPCG_ERR_BREAKDOWN;
+    }
+    if (slice_ptr) {
+        slice_ptr->assign(A->nslices + 1, 0);
+        for (int64_t c = 0; c < A->nslices; ++c)
+            (*slice_ptr)[c + 1] = (*slice_ptr)[c] + (int64_t)width[c] * kSlice;
+    }
+    return SSPCG_OK;
+}
+
+int matrix_fill(sspcg_matrix* A, const double* val, bool values_only, hipStream_t st)
+{
+    const int64_t nrows_padded = A->nslices * kSlice;
+    const int blocks = (int)((nrows_padded + kRowBlock - 1) / kRowBlock);
+    hipLaunchKernelGGL(k_fill, dim3(blocks), dim3(kRowBlock), 0, st, A->n, A->nslices, A->row_ptr,
+                       A->col, val, A->slice_ptr, A->scol, A->sval, A->sval32, values_only);
+    SSPCG_LAUNCHED("k_fill");
+    SSPCG_HIP(hipStreamSynchronize(st));
+    return SSPCG_OK;
+}
+
+template <typename T>
+int launch_mpk_start(int64_t n, const T* r, const T* dinv, T* z1, T* p1, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_mpk_start<T>), dim3(row_grid(n)), dim3(kRowBlock), 0, st, n, r, dinv,
+                       z1, p1);
+    SSPCG_LAUNCHED("k_mpk_start");
+    return SSPCG_OK;
+}
+
+template int launch_mpk_start<double>(int64_t, const double*, const double*, double*, double*,
+                                      hipStream_t);
+template int launch_mpk_start<float>(int64_t, const float*, const float*, float*, float*,
+                                     hipStream_t);
+
+template <typename T>
+int launch_spmv(const sspcg_matrix* A, int mode, const T* x, T* y, const T* zprev, T* znext,
+                double c1, double c2, double c3, const Ctrl* ctrl, hipStream_t st)
+{
+    const Sell<T> S = sell_view<T>(A);
+    const int G = spmv_grid(A);
+    if (mode == 0)
+        hipLaunchKernelGGL((k_spmv<T, 0>), dim3(G), dim3(kRowBlock), 0, st, S, x, y, zprev, znext,
+                           c1, c2, c3, ctrl);
+    else if (mode == 1)
+        hipLaunchKernelGGL((k_spmv<T, 1>), dim3(G), dim3(kRowBlock), 0, st, S, x, y, zprev, znext,
+                           c1, c2, c3, ctrl);
+    else
+        hipLaunchKernelGGL((k_spmv<T, 2>), dim3(G), dim3(kRowBlock), 0, st, S, x, y, zprev, znext,
+                           c1, c2, c3, ctrl);
+    SSPCG_LAUNCHED("k_spmv");
+    return SSPCG_OK;
+}
+
+template int launch_spmv<double>(const sspcg_matrix*, int, const double*, double*, const double*,
+                                 double*, double, double, double, const Ctrl*, hipStream_t);
+template int launch_spmv<float>(const sspcg_matrix*, int, const float*, float*, const float*,
+                                float*, double, double, double, const Ctrl*, hipStream_t);
+
+template <typename TR>
+int launch_residual(const sspcg_matrix* A, const double* x, const double* b, TR* r, TR* z1,
+                    double* partials, int* G_out, hipStream_t st)
+{
+    const Sell<double> S = sell_view<double>(A);
+    const TR* dinvT = sell_view<TR>(A).dinv;
+    const int G = spmv_grid(A);
+    hipLaunchKernelGGL((k_residual<TR>), dim3(G), dim3(kRowBlock), 0, st, S, x, b, r, z1, dinvT,
+                       partials);
+    SSPCG_LAUNCHED("k_residual");
+    *G_out = G;
+    return SSPCG_OK;
+}
+
+template int launch_residual<double>(const sspcg_matrix*, const double*, const double*, double*,
+                                     double*, double*, int*, hipStream_t);
+template int launch_residual<float>(const sspcg_matrix*, const double*, const double*, float*,
+                                    float*, double*, int*, hipStream_t);
+
+int launch_pcg_spmv(const sspcg_matrix* A, const double* p, double* q, double* partials,
+                    int* G_out, const Ctrl* ctrl, hipStream_t st)
+{
+    const int G = spmv_grid(A);
+    hipLaunchKernelGGL(k_pcg_spmv, dim3(G), dim3(kRowBlock), 0, st, sell_view<double>(A), p, q,
+                       partials, ctrl);
+    SSPCG_LAUNCHED("k_pcg_spmv");
+    *G_out = G;
+    return SSPCG_OK;
+}
+
+int launch_pcg_update(const sspcg_matrix* A, int64_t k, double* x, double* r, double* z,
+                      const double* p, const double* q, const double* pq_partials, int Gpq,
+                      double* partials, int* G_out, Ctrl* ctrl, hipStream_t st)
+{
+    const int G = row_grid(A->n);
+    hipLaunchKernelGGL(k_pcg_update, dim3(G), dim3(kRowBlock), 0, st, (int64_t)A->n, k, x, r, z,
+                       p, q, A->dinv, pq_partials, Gpq, partials, ctrl);
+    SSPCG_LAUNCHED("k_pcg_update");
+    *G_out = G;
+    return SSPCG_OK;
+}
+
+int launch_pcg_pupdate(int64_t n, int64_t k, const double* z, double* p, const double* partials,
+                       int G, Ctrl* ctrl, double* hist, hipStream_t st)
+{
+    const int Gp = row_grid(n);
+    hipLaunchKernelGGL(k_pcg_pupdate, dim3(Gp), dim3(kRowBlock), 0, st, n, k, z, p, partials, G,
+                       ctrl, hist);
+    SSPCG_LAUNCHED("k_pcg_pupdate");
+    return SSPCG_OK;
+}
+
+}  // namespace sspcg

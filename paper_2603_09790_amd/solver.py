@@ -1,0 +1,326 @@
+"""Python front end of libsspcg: argument marshalling around the C ABI.
+
+Every numerical step runs in the HIP library; this module only moves torch
+device tensors (memory and the current stream) across the boundary.  Blocks
+of vectors are torch tensors of shape (ncols, ld): row j is column j of the
+n x ncols block, and ld >= n is the leading dimension.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _lib as L
+
+__all__ = ["Matrix", "solve", "pcg", "spmv", "mpk", "block_update_gram", "gram_rect", "fgs",
+           "xr_update", "csr_value_grad", "diffusion7_assemble", "diffusion7_theta_grad",
+           "leading_dim"]
+
+
+def _p(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(device) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _dev(device):
+    if device is None:
+        return torch.device("cuda", torch.cuda.current_device())
+    return torch.device(device)
+
+
+def leading_dim(n: int) -> int:
+    """The leading dimension the solver uses for n-row blocks (n rounded up to 64)."""
+    return (n + 63) // 64 * 64
+
+
+def _dtype_code(t: torch.Tensor) -> int:
+    if t.dtype == torch.float64:
+        return L.F64
+    if t.dtype == torch.float32:
+        return L.F32
+    raise TypeError(f"unsupported dtype {t.dtype}")
+
+
+def _on(t: torch.Tensor, device, dtype=None) -> torch.Tensor:
+    t = torch.as_tensor(t)
+    return t.to(device=device, dtype=dtype or t.dtype).contiguous()
+
+
+class Matrix:
+    """The library's copy of a CSR matrix on one GPU.
+
+    row_ptr / col / val may be numpy arrays or tensors; they are copied to the
+    device and kept alive for the handle's lifetime.  ``fp32=True`` also keeps
+    FP32 values, which the mixed-precision solve and FP32 kernels need.
+    """
+
+    def __init__(self, row_ptr, col, val, *, fp32: bool = False, device=None):
+        self.device = _dev(device)
+        with torch.cuda.device(self.device):
+            self.row_ptr = _on(row_ptr, self.device, torch.int32)
+            self.col = _on(col, self.device, torch.int32)
+            self.val = _on(val, self.device, torch.float64)
+            self.n = self.row_ptr.numel() - 1
+            self.nnz = self.col.numel()
+            self.fp32 = fp32
+            h = ctypes.c_void_p()
+            st = L.lib().sspcg_matrix_create(self.n, self.nnz, _p(self.row_ptr), _p(self.col),
+                                             _p(self.val), L.MATRIX_FP32 if fp32 else 0,
+                                             _stream(self.device), ctypes.byref(h))
+            L.check(st, "sspcg_matrix_create")
+        self.handle = h
+        self._work = None
+        self.values_tag = None
+
+    @classmethod
+    def from_csr(cls, A, **kw) -> "Matrix":
+        """From any object with row_ptr, col and val attributes."""
+        return cls(A.row_ptr, A.col, A.val, **kw)
+
+    def update_values(self, val: torch.Tensor, tag=None) -> None:
+        val = _on(val, self.device, torch.float64)
+        if val.numel() != self.nnz:
+            raise ValueError("value array has the wrong length")
+        with torch.cuda.device(self.device):
+            L.check(L.lib().sspcg_matrix_update_values(self.handle, _p(val), _stream(self.device)),
+                    "sspcg_matrix_update_values")
+        self.val = val
+        self.values_tag = tag
+
+    def info(self) -> dict:
+        n, nnz, slots, nbytes = (ctypes.c_int64() for _ in range(4))
+        L.check(L.lib().sspcg_matrix_info(self.handle, ctypes.byref(n), ctypes.byref(nnz),
+                                          ctypes.byref(slots), ctypes.byref(nbytes)),
+                "sspcg_matrix_info")
+        return dict(n=n.value, nnz=nnz.value, slots=slots.value, device_bytes=nbytes.value)
+
+    def workspace(self, nbytes: int) -> torch.Tensor:
+        if self._work is None or self._work.numel() < nbytes:
+            self._work = None
+            self._work = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        return self._work
+
+    def close(self) -> None:
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            L.lib().sspcg_matrix_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _params(s, sweeps, interval, tol, precision, gram, max_outer, inner_tol, max_refine,
+            check_every, profile=False) -> L.Params:
+    p = L.Params()
+    L.lib().sspcg_default_params(ctypes.byref(p))
+    p.s = int(s)
+    p.sweeps = int(sweeps)
+    p.lambda_min, p.lambda_max = float(interval[0]), float(interval[1])
+    p.tol = float(tol)
+    p.max_outer = int(max_outer)
+    p.precision = {"fp64": L.FP64, "mixed": L.MIXED}[precision]
+    p.inner_tol = float(inner_tol)
+    p.max_refine = int(max_refine)
+    p.gram = {"fgs": L.GRAM_FGS, "cholesky": L.GRAM_CHOLESKY}[gram]
+    p.check_every = int(check_every)
+    p.profile = 1 if profile else 0
+    return p
+
+
+def _result(res: L.Result, st: int) -> dict:
+    return dict(status=st, status_name=L.status_string(st), outer_iters=res.outer_iters,
+                refinements=res.refinements, relres=res.relres, device_ms=res.device_ms)
+
+
+def solve(A: Matrix, b: torch.Tensor, x0: torch.Tensor | None = None, *, s: int = 4,
+          sweeps: int = 2, interval=(0.0, 2.0), tol: float = 1e-8, precision: str = "fp64",
+          gram: str = "fgs", max_outer: int = 20000, inner_tol: float = 1e-4,
+          max_refine: int = 20, check_every: int = 8, history: bool = False,
+          profile: bool = False, out: torch.Tensor | None = None, raise_on_error: bool = True):
+    """s-step PCG (Algorithm 1) on A x = b.  Returns (x, info).
+
+    info['history'] (when history=True): per outer iteration
+    [relres, eta_alpha, eta_beta] (fp64), or the true relative residual per
+    refinement (mixed).  info['profile'] (when profile=True): GPU time and
+    launches per phase, from HIP events around every phase.
+    """
+    p = _params(s, sweeps, interval, tol, precision, gram, max_outer, inner_tol, max_refine,
+                check_every, profile)
+    dev = A.device
+    b = _on(b, dev, torch.float64)
+    if out is None:
+        x = torch.zeros(A.n, dtype=torch.float64, device=dev) if x0 is None \
+            else _on(x0, dev, torch.float64).clone()
+    else:
+        x = out
+        if x0 is not None:
+            x.copy_(x0)
+        else:
+            x.zero_()
+    nbytes = ctypes.c_size_t()
+    L.check(L.lib().sspcg_workspace_bytes(A.handle, ctypes.byref(p), ctypes.byref(nbytes)),
+            "sspcg_workspace_bytes")
+    work = A.workspace(nbytes.value)
+    res = L.Result()
+    nh = (p.max_refine + 1) if precision == "mixed" else 3 * p.max_outer
+    hist = (ctypes.c_double * nh)() if history else None
+    with torch.cuda.device(dev):
+        st = L.lib().sspcg_solve(A.handle, _p(b), _p(x), ctypes.byref(p), _p(work),
+                                 work.numel(), _stream(dev), ctypes.byref(res), hist)
+    if raise_on_error:
+        L.check(st, "sspcg_solve", allow=(L.OK, L.NOT_CONVERGED))
+    info = _result(res, st)
+    if profile:
+        pr = L.Profile()
+        L.check(L.lib().sspcg_last_profile(A.handle, ctypes.byref(pr)), "sspcg_last_profile")
+        info["profile"] = pr.as_dict()
+    if history:
+        import numpy as np
+        h = np.ctypeslib.as_array(hist)
+        if precision == "mixed":
+            info["history"] = h[:res.refinements + 1].copy()
+        else:
+            info["history"] = h[:3 * res.outer_iters].reshape(-1, 3).copy()
+    return x, info
+
+
+def pcg(A: Matrix, b: torch.Tensor, x0: torch.Tensor | None = None, *, tol: float = 1e-8,
+        max_iter: int = 100000, check_every: int = 16, history: bool = False,
+        raise_on_error: bool = True):
+    """Classical Jacobi PCG with the same stop test.  Returns (x, info)."""
+    p = _params(1, 1, (0.0, 2.0), tol, "fp64", "fgs", max_iter, 1e-4, 0, check_every)
+    dev = A.device
+    b = _on(b, dev, torch.float64)
+    x = torch.zeros(A.n, dtype=torch.float64, device=dev) if x0 is None \
+        else _on(x0, dev, torch.float64).clone()
+    nbytes = ctypes.c_size_t()
+    L.check(L.lib().sspcg_workspace_bytes(A.handle, ctypes.byref(p), ctypes.byref(nbytes)),
+            "sspcg_workspace_bytes")
+    work = A.workspace(nbytes.value)
+    res = L.Result()
+    hist = (ctypes.c_double * max_iter)() if history else None
+    with torch.cuda.device(dev):
+        st = L.lib().sspcg_pcg_solve(A.handle, _p(b), _p(x), ctypes.byref(p), _p(work),
+                                     work.numel(), _stream(dev), ctypes.byref(res), hist)
+    if raise_on_error:
+        L.check(st, "sspcg_pcg_solve", allow=(L.OK, L.NOT_CONVERGED))
+    info = _result(res, st)
+    if history:
+        import numpy as np
+        info["history"] = np.ctypeslib.as_array(hist)[:res.outer_iters].copy()
+    return x, info
+
+
+# ------------------------------------------------------------------ kernels
+
+def _kwork(s: int, device) -> torch.Tensor:
+    return torch.empty(L.lib().sspcg_kernel_work_bytes(s), dtype=torch.uint8, device=device)
+
+
+def spmv(A: Matrix, x: torch.Tensor) -> torch.Tensor:
+    """y = A x (float64, or float32 values/vectors with FP64 sums)."""
+    y = torch.empty_like(x)
+    with torch.cuda.device(A.device):
+        L.check(L.lib().sspcg_spmv(A.handle, _dtype_code(x), _p(x), _p(y), _stream(A.device)),
+                "sspcg_spmv")
+    return y
+
+
+def mpk(A: Matrix, r: torch.Tensor, s: int, interval, ld: int | None = None):
+    """Algorithm 2: returns Z (s, ld) and P (s+1, ld)."""
+    ld = ld or A.n
+    Z = torch.zeros((s, ld), dtype=r.dtype, device=A.device)
+    P = torch.zeros((s + 1, ld), dtype=r.dtype, device=A.device)
+    with torch.cuda.device(A.device):
+        L.check(L.lib().sspcg_mpk(A.handle, _dtype_code(r), _p(r), s, float(interval[0]),
+                                  float(interval[1]), _p(Z), _p(P), ld, _stream(A.device)),
+                "sspcg_mpk")
+    return Z, P
+
+
+def block_update_gram(n: int, Z, Q, AZ, AQ, beta, r):
+    """In place Q <- Z + Q beta, AQ <- AZ + AQ beta (beta None: Q <- Z, AQ <- AZ);
+    returns W = Q^T AQ (s, s) and b1 = Q^T r (s,), float64."""
+    s, ld = Q.shape
+    dev = Q.device
+    W = torch.empty((s, s), dtype=torch.float64, device=dev)
+    b1 = torch.empty(s, dtype=torch.float64, device=dev)
+    work = _kwork(s, dev)
+    beta = None if beta is None else _on(beta, dev, torch.float64)
+    with torch.cuda.device(dev):
+        L.check(L.lib().sspcg_block_update_gram(n, s, _dtype_code(Q), _p(Z), _p(Q), _p(AZ), _p(AQ),
+                                                _p(beta), _p(r), ld, _p(W), _p(b1), _p(work),
+                                                work.numel(), _stream(dev)),
+                "sspcg_block_update_gram")
+    return W, b1
+
+
+def gram_rect(n: int, Q, AZ):
+    """B2 = -Q^T AZ (s, s) float64."""
+    s, ld = Q.shape
+    dev = Q.device
+    B2 = torch.empty((s, s), dtype=torch.float64, device=dev)
+    work = _kwork(s, dev)
+    with torch.cuda.device(dev):
+        L.check(L.lib().sspcg_gram_rect(n, s, _dtype_code(Q), _p(Q), _p(AZ), ld, _p(B2), _p(work),
+                                        work.numel(), _stream(dev)), "sspcg_gram_rect")
+    return B2
+
+
+def fgs(W: torch.Tensor, B: torch.Tensor, sweeps: int, solver: str = "fgs"):
+    """FGS (or Cholesky) solve of W X = B on the device.  Returns (X, status)."""
+    s = W.shape[0]
+    vec = B.dim() == 1
+    Bm = B.reshape(s, -1).contiguous()
+    X = torch.empty_like(Bm)
+    status = torch.zeros(1, dtype=torch.int32, device=W.device)
+    with torch.cuda.device(W.device):
+        L.check(L.lib().sspcg_fgs(s, Bm.shape[1], _p(W.contiguous()), _p(Bm), sweeps,
+                                  {"fgs": L.GRAM_FGS, "cholesky": L.GRAM_CHOLESKY}[solver],
+                                  _p(X), _p(status), _stream(W.device)), "sspcg_fgs")
+    return (X.reshape(-1) if vec else X), int(status.item())
+
+
+def xr_update(A: Matrix, Q, AQ, alpha, x, r, z1=None) -> float:
+    """In place x += Q alpha, r -= AQ alpha (and z1 = M^{-1} r); returns ||r||^2."""
+    s, ld = Q.shape
+    rr = torch.empty(1, dtype=torch.float64, device=A.device)
+    work = _kwork(s, A.device)
+    with torch.cuda.device(A.device):
+        L.check(L.lib().sspcg_xr_update(A.handle, s, _dtype_code(Q), _p(Q), _p(AQ),
+                                        _p(_on(alpha, A.device, torch.float64)), ld, _p(x), _p(r),
+                                        _p(z1), _p(rr), _p(work), work.numel(),
+                                        _stream(A.device)), "sspcg_xr_update")
+    return float(rr.item())
+
+
+def csr_value_grad(A: Matrix, lam: torch.Tensor, x: torch.Tensor) -> torch.Tensor:
+    g = torch.empty(A.nnz, dtype=torch.float64, device=A.device)
+    with torch.cuda.device(A.device):
+        L.check(L.lib().sspcg_csr_value_grad(A.handle, _p(lam), _p(x), _p(g), _stream(A.device)),
+                "sspcg_csr_value_grad")
+    return g
+
+
+def diffusion7_assemble(A: Matrix, theta: torch.Tensor) -> torch.Tensor:
+    val = torch.empty(A.nnz, dtype=torch.float64, device=A.device)
+    with torch.cuda.device(A.device):
+        L.check(L.lib().sspcg_diffusion7_assemble(A.handle, _p(theta), _p(val), _stream(A.device)),
+                "sspcg_diffusion7_assemble")
+    return val
+
+
+def diffusion7_theta_grad(A: Matrix, theta: torch.Tensor, gval: torch.Tensor) -> torch.Tensor:
+    g = torch.empty(A.n, dtype=torch.float64, device=A.device)
+    with torch.cuda.device(A.device):
+        L.check(L.lib().sspcg_diffusion7_theta_grad(A.handle, _p(theta), _p(gval), _p(g),
+                                                    _stream(A.device)),
+                "sspcg_diffusion7_theta_grad")
+    return g

@@ -1,0 +1,314 @@
+"""Kernel-level parity of the HIP library against the CPU oracle.
+
+Teacher forcing: the oracle's own states at outer iteration k (from
+oracle_trace) are fed to each GPU kernel through the C ABI, and the GPU
+output is compared with the oracle's next state.  Tolerances:
+  * vectors: |d| <= 1e-12 * max|ref| per column (FMA contraction and the
+    MPK's M^{-1}-folded Chebyshev update differ from the oracle in rounding);
+  * Gram entries (W, b1, B2): |d_ij| <= 1e-12 * sum_r |Q_ri| |AQ_rj|, the
+    forward-error scale of a dot product, since entries can cancel;
+  * FP32 SpMV: bit-exact (same order, exact products, one rounding).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2603_09790_amd as P
+import sspcg_inputs as si
+from oracle_trace import trace
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def gpu(a, dtype=None):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV, dtype=dtype)
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def block(a, ld):
+    """Oracle block (ncols, n) -> device tensor (ncols, ld), zero padded."""
+    t = torch.zeros((a.shape[0], ld), dtype=torch.float64, device=DEV)
+    t[:, :a.shape[1]] = gpu(a)
+    return t
+
+
+def col_close(got, ref, tol):
+    got, ref = np.atleast_2d(got), np.atleast_2d(ref)
+    for j in range(ref.shape[0]):
+        scale = max(np.abs(ref[j]).max(), 1e-300)
+        err = np.abs(got[j] - ref[j]).max()
+        assert err <= tol * scale, f"column {j}: {err / scale:.3e} > {tol}"
+
+
+def gram_close(got, ref, Q, AQ, tol=1e-12):
+    scale = np.abs(Q) @ np.abs(AQ).T
+    err = np.abs(got - ref)
+    assert np.all(err <= tol * scale + 1e-300), f"max scaled err {np.max(err / scale):.3e}"
+
+
+SYSTEMS = {
+    # name: (kind, N, coefficients)  -- n values include ragged tails (not multiples of 64)
+    "p5_64": ("5pt", 64, None),
+    "d7_13": ("7pt", 13, "theta"),
+    "d27_17": ("27pt", 17, "blocks"),
+}
+
+
+def system(name):
+    kind, N, coef = SYSTEMS[name]
+    n = N * N if kind == "5pt" else N**3
+    kap = None
+    if coef == "theta":
+        kap = np.exp(si.theta_field(n))
+    elif coef == "blocks":
+        rng = np.random.default_rng(1)
+        kap = 10.0 ** rng.uniform(-2, 2, n)
+    A = si.stencil(kind, N, kap)
+    b = si.rhs_normal(A.n)
+    return A, b, si.lanczos_bounds(A)
+
+
+@pytest.fixture(scope="module", params=list(SYSTEMS))
+def sys_(request):
+    A, b, interval = system(request.param)
+    return A, b, interval, P.Matrix.from_csr(A, fp32=True, device=DEV)
+
+
+def test_spmv_fp64(sys_):
+    A, _, _, M = sys_
+    x = np.random.default_rng(5).normal(size=A.n)
+    y = host(P.spmv(M, gpu(x)))
+    ref = oracle.spmv(A, x)
+    absA = A.__class__(A.n, A.row_ptr, A.col, np.abs(A.val), A.shape3)
+    scale = oracle.spmv(absA, np.abs(x))
+    assert np.all(np.abs(y - ref) <= 1e-14 * scale)
+
+
+def test_spmv_fp32_bit_exact(sys_):
+    A, _, _, M = sys_
+    x32 = np.random.default_rng(6).normal(size=A.n).astype(np.float32)
+    y = host(P.spmv(M, gpu(x32)))
+    ref = oracle.spmv_f32(A, A.val.astype(np.float32), x32)
+    assert np.array_equal(y, ref)
+
+
+def test_matrix_info_and_padding(sys_):
+    A, _, _, M = sys_
+    info = M.info()
+    assert info["n"] == A.n and info["nnz"] == A.nnz
+    assert A.nnz <= info["slots"] <= 1.2 * A.nnz + 64 * 27
+
+
+@pytest.mark.parametrize("s", [1, 2, 4, 6, 8, 16])
+def test_mpk(sys_, s):
+    A, b, interval, M = sys_
+    dinv = oracle.jacobi_inverse(A)
+    r = np.random.default_rng(7).uniform(-1, 1, A.n)
+    Zr, Pr = oracle.mpk(A, dinv, r, s, interval)
+    ld = P.leading_dim(A.n)
+    Z, Pm = P.mpk(M, gpu(r), s, interval, ld=ld)
+    Z, Pm = host(Z)[:, :A.n], host(Pm)[:, :A.n]
+    tol = 1e-12 if s <= 8 else 1e-10
+    col_close(Z, Zr, tol)
+    col_close(Pm, Pr, tol)
+    assert np.array_equal(Pm[0], r)
+
+
+def test_mpk_fp32(sys_):
+    A, _, interval, M = sys_
+    s = 4
+    d = A.val.astype(np.float32)
+    dinv32 = (1.0 / si.to_scipy(A).diagonal()).astype(np.float32)
+    r32 = np.random.default_rng(8).uniform(-1, 1, A.n).astype(np.float32)
+    Zr, Pr = oracle.mpk_f32(A, d, dinv32, r32, s, interval)
+    Z, Pm = P.mpk(M, gpu(r32), s, interval)
+    # FP32 storage: the GPU folds M^{-1} into the recurrence, the oracle keeps
+    # zp; both round every stored vector to FP32
+    col_close(host(Z), Zr.astype(np.float64), 2e-5)
+    col_close(host(Pm), Pr.astype(np.float64), 2e-5)
+
+
+@pytest.fixture(scope="module")
+def traced():
+    out = {}
+    for name in SYSTEMS:
+        A, b, interval = system(name)
+        for s in (2, 6):
+            _, _, states = trace(A, b, s=s, sweeps=2, interval=interval, tol=1e-14, max_outer=12)
+            out[(name, s)] = (A, interval, states, P.Matrix.from_csr(A, device=DEV))
+    return out
+
+
+KEYS = [(n, s) for n in SYSTEMS for s in (2, 6)]
+
+
+@pytest.mark.parametrize("key", KEYS)
+def test_first_block_gram(traced, key):
+    A, _, states, M = traced[key]
+    st = states[0]
+    ld = P.leading_dim(A.n)
+    s = st["Z"].shape[0]
+    Z, AZ = block(st["Z"], ld), block(st["P"][1:], ld)
+    Q = torch.full_like(Z, float("nan"))
+    AQ = torch.full_like(Z, float("nan"))
+    r = gpu(st["P"][0])
+    W, b1 = P.block_update_gram(A.n, Z, Q, AZ, AQ, None, r)
+    assert torch.equal(Q[:, :A.n], Z[:, :A.n]) and torch.equal(AQ[:, :A.n], AZ[:, :A.n])
+    gram_close(host(W), st["W"], st["Q"], st["AQ"])
+    gram_close(host(b1)[:, None], st["b1"][:, None], st["Q"], st["r"][None, :])
+    assert np.array_equal(host(W), host(W).T)
+
+
+@pytest.mark.parametrize("key", KEYS)
+@pytest.mark.parametrize("k", [0, 1, 5, 10])
+def test_update_gram_and_rect(traced, key, k):
+    A, _, states, M = traced[key]
+    st, nx = states[k], states[k + 1]
+    ld = P.leading_dim(A.n)
+    Q, AQ = block(st["Q"], ld), block(st["AQ"], ld)
+    Z, AZ = block(st["Znext"], ld), block(st["Pnext"][1:], ld)
+    B2 = P.gram_rect(A.n, Q, AZ)
+    gram_close(host(B2), st["B2"], st["Q"], st["Pnext"][1:])
+    W, b1 = P.block_update_gram(A.n, Z, Q, AZ, AQ, gpu(st["beta"]), gpu(st["Pnext"][0]))
+    col_close(host(Q)[:, :A.n], nx["Q"], 1e-12)
+    col_close(host(AQ)[:, :A.n], nx["AQ"], 1e-12)
+    gram_close(host(W), nx["W"], nx["Q"], nx["AQ"])
+    gram_close(host(b1)[:, None], nx["b1"][:, None], nx["Q"], nx["r"][None, :])
+
+
+@pytest.mark.parametrize("key", KEYS)
+@pytest.mark.parametrize("k", [0, 3, 10])
+def test_fgs_on_oracle_systems(traced, key, k):
+    _, _, states, _ = traced[key]
+    st = states[k]
+    for sweeps in (1, 2, 3, 30):
+        a, code = P.fgs(gpu(st["W"]), gpu(st["b1"]), sweeps)
+        ar, _ = oracle.fgs(st["W"], st["b1"], sweeps)
+        assert code == 0
+        assert np.abs(host(a) - ar).max() <= 1e-12 * np.abs(ar).max()
+        B, code = P.fgs(gpu(st["W"]), gpu(st["B2"]), sweeps)
+        Br, _ = oracle.fgs(st["W"], st["B2"], sweeps)
+        assert np.abs(host(B) - Br).max() <= 1e-12 * np.abs(Br).max()
+    a, code = P.fgs(gpu(st["W"]), gpu(st["b1"]), 1, solver="cholesky")
+    ar, _ = oracle.chol_solve(st["W"], st["b1"])
+    assert np.abs(host(a) - ar).max() <= 1e-10 * np.abs(ar).max()
+
+
+def test_fgs_status_flags():
+    W = np.eye(4)
+    W[2, 2] = 0.0
+    _, code = P.fgs(gpu(W), gpu(np.ones(4)), 2)
+    assert code == P.ERR_BREAKDOWN
+    _, code = P.fgs(gpu(np.eye(4)), gpu(np.array([1.0, np.nan, 0, 0])), 2)
+    assert code == P.ERR_NONFINITE
+    _, code = P.fgs(gpu(-np.eye(3)), gpu(np.ones(3)), 1, solver="cholesky")
+    assert code == P.ERR_BREAKDOWN
+
+
+@pytest.mark.parametrize("key", KEYS)
+@pytest.mark.parametrize("k", [0, 4])
+def test_xr_update(traced, key, k):
+    A, _, states, M = traced[key]
+    st, nx = states[k], states[k + 1]
+    ld = P.leading_dim(A.n)
+    x, r = gpu(st["x"]), gpu(st["r"])
+    z1 = torch.empty_like(x)
+    rr = P.xr_update(M, block(st["Q"], ld), block(st["AQ"], ld), gpu(st["alpha"]), x, r, z1)
+    col_close(host(x), nx["x"], 1e-13)
+    col_close(host(r), nx["r"], 1e-12)
+    col_close(host(z1), st["Znext"][0], 1e-12)
+    assert abs(rr - oracle.dot(nx["r"], nx["r"])) <= 1e-12 * rr
+
+
+@pytest.mark.parametrize("key", KEYS)
+@pytest.mark.parametrize("k", [0, 2, 7])
+def test_one_outer_iteration(traced, key, k):
+    """Step-level teacher forcing: one GPU outer iteration from oracle state k."""
+    A, interval, states, M = traced[key]
+    st, nx = states[k], states[k + 1]
+    s = st["Q"].shape[0]
+    ld = P.leading_dim(A.n)
+    x, r = gpu(st["x"]), gpu(st["r"])
+    Q, AQ = block(st["Q"], ld), block(st["AQ"], ld)
+    P.xr_update(M, Q, AQ, gpu(st["alpha"]), x, r)
+    Z, Pm = P.mpk(M, r, s, interval, ld=ld)
+    B2 = P.gram_rect(A.n, Q, Pm[1:])
+    beta, code = P.fgs(gpu(st["W"]), B2, 2)
+    assert code == 0
+    W, b1 = P.block_update_gram(A.n, Z, Q, Pm[1:], AQ, beta, Pm[0])
+    alpha, code = P.fgs(W, b1, 2)
+    col_close(host(x), nx["x"], 1e-12)
+    col_close(host(r), nx["r"], 1e-11)
+    col_close(host(Q)[:, :A.n], nx["Q"], 1e-10)
+    col_close(host(AQ)[:, :A.n], nx["AQ"], 1e-10)
+    assert np.abs(host(W) - nx["W"]).max() <= 1e-10 * np.abs(nx["W"]).max()
+    assert np.abs(host(alpha) - nx["alpha"]).max() <= 1e-9 * np.abs(nx["alpha"]).max()
+
+
+def test_fp32_gram_kernels_match_upcast_oracle():
+    A, _, interval = system("d7_13")
+    s = 4
+    rng = np.random.default_rng(9)
+    Z = rng.normal(size=(s, A.n)).astype(np.float32)
+    AZ = rng.normal(size=(s, A.n)).astype(np.float32)
+    Q = rng.normal(size=(s, A.n)).astype(np.float32)
+    AQ = rng.normal(size=(s, A.n)).astype(np.float32)
+    r = rng.normal(size=A.n).astype(np.float32)
+    beta = rng.normal(size=(s, s)) * 0.3
+    B2 = P.gram_rect(A.n, gpu(Q), gpu(AZ))
+    gram_close(host(B2), oracle.gram_rect(Q, AZ), Q.astype(float), AZ.astype(float))
+    Qo, AQo = Q.copy(), AQ.copy()
+    oracle.block_update(Z, Qo, AZ, AQo, beta)
+    Qg, AQg = gpu(Q), gpu(AQ)
+    W, b1 = P.block_update_gram(A.n, gpu(Z), Qg, gpu(AZ), AQg, gpu(beta), gpu(r))
+    # each element is one FP32 rounding of nearly the same FP64 value
+    d = np.abs(host(Qg).astype(np.float64) - Qo.astype(np.float64))
+    assert np.all(d <= np.spacing(np.abs(Qo)).astype(np.float64) * 1.0001)
+    Wr, br = oracle.gram(host(Qg), host(AQg), r)
+    gram_close(host(W), Wr, host(Qg).astype(float), host(AQg).astype(float))
+
+
+# ------------------------------------------------------------- differentiation
+def test_diffusion_kernels_match_oracle():
+    N = 9
+    theta = si.theta_field(N**3)
+    A = si.stencil("7pt", N, np.exp(theta))
+    M = P.Matrix.from_csr(A, device=DEV)
+    val = host(P.diffusion7_assemble(M, gpu(theta)))
+    ref = oracle.diffusion7_assemble(A, theta)
+    assert np.abs(val - ref).max() <= 1e-14 * np.abs(ref).max()
+    rng = np.random.default_rng(10)
+    lam, x = rng.normal(size=A.n), rng.normal(size=A.n)
+    g = host(P.csr_value_grad(M, gpu(lam), gpu(x)))
+    assert np.array_equal(g, oracle.csr_value_grad(A, lam, x))
+    gt = host(P.diffusion7_theta_grad(M, gpu(theta), gpu(g)))
+    gr = oracle.diffusion7_theta_grad(A, theta, g)
+    assert np.abs(gt - gr).max() <= 1e-12 * np.abs(gr).max()
+
+
+def test_matrix_create_rejects_bad_input():
+    A = si.poisson5(8)
+    bad = A.val.copy()
+    bad[A.row_ptr[3]] *= 1.0
+    d = A.col == np.repeat(np.arange(A.n), np.diff(A.row_ptr))
+    neg = A.val.copy()
+    neg[np.flatnonzero(d)[5]] *= -1
+    with pytest.raises(P.SSPCGError) as e:
+        P.Matrix(A.row_ptr, A.col, neg, device=DEV)
+    assert e.value.status == P.ERR_BREAKDOWN
+    col = A.col.copy()
+    col[7] = A.n + 3
+    with pytest.raises(P.SSPCGError) as e:
+        P.Matrix(A.row_ptr, col, A.val, device=DEV)
+    assert e.value.status == P.ERR_ARG
+    nanv = A.val.copy()
+    nanv[2] = np.nan
+    with pytest.raises(P.SSPCGError) as e:
+        P.Matrix(A.row_ptr, A.col, nanv, device=DEV)
+    assert e.value.status == P.ERR_NONFINITE

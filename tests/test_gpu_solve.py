@@ -1,0 +1,282 @@
+"""Solver-level parity of the HIP s-step PCG against the CPU oracle.
+
+At small sweep counts (nu <= 3) the s-step iteration amplifies rounding
+differences during the run (the Gram solves are inexact), so GPU and oracle
+iterates separate in mid-run and meet again near the solution.  The checks
+are therefore: the early trajectory (first 20 outer iterations) within
+1e-10; solutions at a tight tolerance (relative residual 1e-12) within
+1e-10; trajectory-stable settings (classical PCG, nu = 30, Cholesky Gram
+solve) within 1e-10 at tolerance 1e-8.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2603_09790_amd as P
+import sspcg_inputs as si
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def gpu(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+@pytest.fixture(scope="module")
+def poisson5():
+    w = si.workload("poisson5")
+    w["M"] = P.Matrix.from_csr(w["A"], fp32=True, device=DEV)
+    return w
+
+
+@pytest.fixture(scope="module")
+def poisson7():
+    w = si.workload("poisson7", N=24)
+    w["M"] = P.Matrix.from_csr(w["A"], fp32=True, device=DEV)
+    return w
+
+
+@pytest.fixture(scope="module")
+def diffusion27():
+    N = 24
+    A = si.stencil("27pt", N, si.coeff_blocks(N))
+    w = dict(A=A, b=si.rhs_normal(A.n), interval=si.lanczos_bounds(A))
+    w["M"] = P.Matrix.from_csr(A, fp32=True, device=DEV)
+    return w
+
+
+def run(w, **kw):
+    x, info = P.solve(w["M"], gpu(w["b"]), interval=w["interval"], **kw)
+    return x.cpu().numpy(), info
+
+
+def test_early_trajectory_poisson5(poisson5):
+    w = poisson5
+    x, info = run(w, s=4, sweeps=2, tol=1e-30, max_outer=20)
+    xo, ro = oracle.sspcg(w["A"], w["b"], s=4, sweeps=2, interval=w["interval"], tol=1e-30,
+                          max_outer=20)
+    assert info["status"] == P.NOT_CONVERGED and ro["status"] == oracle.NOT_CONVERGED
+    assert info["outer_iters"] == 20
+    assert rel(x, xo) <= 1e-10
+
+
+@pytest.mark.parametrize("name", ["poisson5", "poisson7", "diffusion27"])
+def test_tight_tolerance_solution(name, request):
+    w = request.getfixturevalue(name)
+    s = 6 if name == "diffusion27" else 4
+    x, info = run(w, s=s, sweeps=2, tol=1e-12)
+    xo, ro = oracle.sspcg(w["A"], w["b"], s=s, sweeps=2, interval=w["interval"], tol=1e-12)
+    assert info["status"] == P.OK and ro["status"] == oracle.OK
+    assert info["relres"] <= 1e-12
+    assert rel(x, xo) <= 1e-10
+    # the iteration counts of two runs that differ only in rounding
+    assert abs(info["outer_iters"] - ro["iters"]) <= max(5, 0.1 * ro["iters"])
+
+
+@pytest.mark.parametrize("s", [2, 4, 6, 8])
+@pytest.mark.parametrize("sweeps", [1, 2, 3])
+def test_s_nu_grid(poisson7, s, sweeps):
+    w = poisson7
+    x, info = run(w, s=s, sweeps=sweeps, tol=1e-12)
+    xo, ro = oracle.sspcg(w["A"], w["b"], s=s, sweeps=sweeps, interval=w["interval"], tol=1e-12)
+    assert info["status"] == ro["status"] == 0
+    assert rel(x, xo) <= 1e-10
+
+
+@pytest.mark.parametrize("gram,sweeps", [("fgs", 30), ("cholesky", 1)])
+def test_trajectory_stable_settings(poisson5, gram, sweeps):
+    w = poisson5
+    x, info = run(w, s=4, sweeps=sweeps, gram=gram, tol=1e-8, history=True)
+    xo, ro, ho = oracle.sspcg(w["A"], w["b"], s=4, sweeps=sweeps, interval=w["interval"],
+                              tol=1e-8, gram=gram, history=True)
+    assert info["outer_iters"] == ro["iters"]
+    assert rel(x, xo) <= 1e-10
+    h = info["history"]
+    assert np.abs(h[:, 0] - ho[:, 0]).max() <= 1e-9 * ho[0, 0]
+
+
+def test_history_matches_oracle_early(poisson7):
+    w = poisson7
+    _, info = run(w, s=4, sweeps=2, tol=1e-30, max_outer=10, history=True)
+    _, _, ho = oracle.sspcg(w["A"], w["b"], s=4, sweeps=2, interval=w["interval"], tol=1e-30,
+                            max_outer=10, history=True)
+    h = info["history"]
+    assert h.shape == (10, 3)
+    assert np.allclose(h[:, 0], ho[:, 0], rtol=1e-9, atol=0)
+    assert np.allclose(h[:, 1], ho[:, 1], rtol=1e-6, atol=1e-12)
+    assert np.allclose(h[:-1, 2], ho[:-1, 2], rtol=1e-6, atol=1e-12)
+
+
+@pytest.mark.parametrize("name", ["poisson5", "diffusion27"])
+def test_classical_pcg(name, request):
+    w = request.getfixturevalue(name)
+    x, info = P.pcg(w["M"], gpu(w["b"]), tol=1e-8, history=True)
+    xo, ro, ho = oracle.pcg(w["A"], w["b"], tol=1e-8, history=True)
+    assert info["status"] == P.OK
+    assert abs(info["outer_iters"] - ro["iters"]) <= 1
+    assert rel(x.cpu().numpy(), xo) <= 1e-10
+    k = min(len(ho), len(info["history"])) - 2
+    assert np.allclose(info["history"][:k], ho[:k], rtol=1e-8)
+
+
+def test_s1_is_classical_pcg(poisson5):
+    w = poisson5
+    x1, i1 = run(w, s=1, sweeps=3, tol=1e-8)
+    x2, i2 = P.pcg(w["M"], gpu(w["b"]), tol=1e-8)
+    assert abs(i1["outer_iters"] - i2["outer_iters"]) <= 1
+    assert rel(x1, x2.cpu().numpy()) <= 1e-9
+
+
+def test_deterministic(diffusion27):
+    w = diffusion27
+    x1, i1 = run(w, s=6, sweeps=2, tol=1e-8)
+    x2, i2 = run(w, s=6, sweeps=2, tol=1e-8)
+    assert i1["outer_iters"] == i2["outer_iters"]
+    assert np.array_equal(x1, x2)
+
+
+@pytest.mark.parametrize("name", ["poisson7", "diffusion27"])
+def test_mixed_precision_refinement(name, request):
+    w = request.getfixturevalue(name)
+    x, info = run(w, s=4, sweeps=2, tol=1e-10, precision="mixed", history=True)
+    assert info["status"] == P.OK and info["relres"] <= 1e-10
+    assert 1 <= info["refinements"] <= 8
+    h = info["history"]
+    assert h[-1] <= 1e-10 and np.all(np.diff(h) < 0)
+    # true residual recomputed independently
+    r = w["b"] - oracle.spmv(w["A"], x)
+    assert np.linalg.norm(r) <= 1.0001e-10 * np.linalg.norm(w["b"])
+    xo, ro = oracle.sspcg(w["A"], w["b"], s=4, sweeps=2, interval=w["interval"], tol=1e-13)
+    err = rel(x, xo)
+    print(f"{name}: mixed vs FP64 oracle relative error {err:.2e}, "
+          f"{info['refinements']} refinements, {info['outer_iters']} inner iterations")
+    assert err < 1e-7
+    xm, rm = oracle.sspcg_mixed(w["A"], w["b"], s=4, sweeps=2, interval=w["interval"], tol=1e-10)
+    assert rm["status"] == oracle.OK
+    assert abs(rm["refinements"] - info["refinements"]) <= 2
+
+
+def test_mixed_needs_fp32_values(poisson5):
+    M = P.Matrix.from_csr(poisson5["A"], device=DEV)
+    with pytest.raises(P.SSPCGError) as e:
+        P.solve(M, gpu(poisson5["b"]), interval=poisson5["interval"], precision="mixed")
+    assert e.value.status == P.ERR_UNSUPPORTED
+
+
+# ------------------------------------------------------------------ edge cases
+def test_zero_rhs_gives_zero(poisson5):
+    x, info = P.solve(poisson5["M"], torch.zeros(4096, dtype=torch.float64, device=DEV),
+                      x0=torch.ones(4096, dtype=torch.float64, device=DEV),
+                      interval=poisson5["interval"])
+    assert info["status"] == P.OK and info["outer_iters"] == 0
+    assert torch.count_nonzero(x).item() == 0
+
+
+def test_exact_start_takes_no_iteration(poisson5):
+    w = poisson5
+    xs, _ = oracle.pcg(w["A"], w["b"], tol=1e-14)
+    x, info = P.solve(w["M"], gpu(w["b"]), x0=gpu(xs), interval=w["interval"], tol=1e-8)
+    assert info["status"] == P.OK and info["outer_iters"] == 0
+    assert np.array_equal(x.cpu().numpy(), xs)
+
+
+def test_nonfinite_rhs(poisson5):
+    b = poisson5["b"].copy()
+    b[17] = np.nan
+    _, info = P.solve(poisson5["M"], gpu(b), interval=poisson5["interval"], raise_on_error=False)
+    assert info["status"] == P.ERR_NONFINITE
+
+
+def test_iteration_limit(poisson5):
+    x, info = run(poisson5, s=4, sweeps=2, tol=1e-8, max_outer=1)
+    assert info["status"] == P.NOT_CONVERGED and info["outer_iters"] == 1
+    xo, ro = oracle.sspcg(poisson5["A"], poisson5["b"], s=4, sweeps=2,
+                          interval=poisson5["interval"], tol=1e-8, max_outer=1)
+    assert rel(x, xo) <= 1e-12
+
+
+@pytest.mark.parametrize("kind,N,s", [("5pt", 3, 2), ("5pt", 9, 16), ("7pt", 5, 3),
+                                      ("27pt", 4, 5)])
+def test_small_and_ragged_systems(kind, N, s):
+    A = si.stencil(kind, N)
+    b = si.rhs_uniform(A.n)
+    lo, hi = si.closed_form_bounds(kind, N)
+    M = P.Matrix.from_csr(A, device=DEV)
+    x, info = P.solve(M, gpu(b), s=s, sweeps=8, interval=(lo * 0.99, hi * 1.01), tol=1e-11)
+    xo, ro = oracle.sspcg(A, b, s=s, sweeps=8, interval=(lo * 0.99, hi * 1.01), tol=1e-11)
+    assert info["status"] == ro["status"] == 0
+    assert rel(x.cpu().numpy(), xo) <= 1e-9
+
+
+def test_workspace_too_small(poisson5):
+    import ctypes
+    from paper_2603_09790_amd import _lib as L
+    p = L.Params()
+    L.lib().sspcg_default_params(ctypes.byref(p))
+    p.lambda_max = 2.0
+    b = gpu(poisson5["b"])
+    x = torch.zeros_like(b)
+    work = torch.empty(1024, dtype=torch.uint8, device=DEV)
+    res = L.Result()
+    st = L.lib().sspcg_solve(poisson5["M"].handle, ctypes.c_void_p(b.data_ptr()),
+                             ctypes.c_void_p(x.data_ptr()), ctypes.byref(p),
+                             ctypes.c_void_p(work.data_ptr()), 1024, None, ctypes.byref(res), None)
+    assert st == L.ERR_WORKSPACE
+
+
+# ------------------------------------------------------------ differentiation
+def test_diffusion_solve_gradient():
+    N = 8
+    theta = si.theta_field(N**3)
+    A = si.stencil("7pt", N, np.exp(theta))
+    b = si.rhs_uniform(A.n)
+    xt = si.x_target(A.n)
+    interval = si.lanczos_bounds(A)
+    M = P.Matrix.from_csr(A, device=DEV)
+    opts = dict(s=4, sweeps=2, interval=interval, tol=1e-13)
+    th = gpu(theta).requires_grad_(True)
+    x = P.DiffusionSolve.apply(th, gpu(b), M, opts)
+    loss = 0.5 * torch.sum((x - gpu(xt)) ** 2)
+    loss.backward()
+    g = th.grad.cpu().numpy()
+    # oracle chain: solve, adjoint solve, value gradient, theta gradient
+    xo, _ = oracle.sspcg(A, b, s=4, sweeps=2, interval=interval, tol=1e-14)
+    lam, _ = oracle.sspcg(A, xo - xt, s=4, sweeps=2, interval=interval, tol=1e-14)
+    go = oracle.diffusion7_theta_grad(A, theta, oracle.csr_value_grad(A, lam, xo))
+    assert rel(g, go) <= 1e-8
+    # central finite differences of the loss along a unit direction
+    u = si.unit_direction(A.n)
+    h = 1e-5
+
+    def loss_at(t):
+        Ah = si.stencil("7pt", N, np.exp(t))
+        xh, _ = oracle.sspcg(Ah, b, s=4, sweeps=2, interval=interval, tol=1e-14)
+        return 0.5 * np.sum((xh - xt) ** 2)
+
+    fd = (loss_at(theta + h * u) - loss_at(theta - h * u)) / (2 * h)
+    assert abs(fd - g @ u) <= 1e-6 * abs(g @ u)
+
+
+def test_sparse_solve_value_and_rhs_gradient():
+    N = 6
+    A = si.stencil("7pt", N, np.exp(si.theta_field(N**3)))
+    b = si.rhs_uniform(A.n)
+    interval = si.lanczos_bounds(A)
+    M = P.Matrix.from_csr(A, device=DEV)
+    val = gpu(A.val).requires_grad_(True)
+    bb = gpu(b).requires_grad_(True)
+    x = P.SparseSolve.apply(val, bb, M, dict(s=3, sweeps=3, interval=interval, tol=1e-13))
+    w = torch.linspace(-1, 1, A.n, dtype=torch.float64, device=DEV)
+    (x * w).sum().backward()
+    D = si.to_scipy(A).toarray()
+    lam = np.linalg.solve(D, w.cpu().numpy())
+    xs = np.linalg.solve(D, b)
+    assert rel(bb.grad.cpu().numpy(), lam) <= 1e-9
+    rows = np.repeat(np.arange(A.n), np.diff(A.row_ptr))
+    assert rel(val.grad.cpu().numpy(), -lam[rows] * xs[A.col]) <= 1e-9
