@@ -34,17 +34,27 @@ def log(msg: str) -> None:
     print(msg, file=sys.stderr, flush=True)
 
 
-def spmv_family_bytes(n: int, nnz: int, s: int, elem: int) -> float:
-    """Algorithmic bytes of one matrix powers kernel (s SpMV launches).
+def spmv_bytes(n: int, nnz: int, elem: int, col_frac: float) -> float:
+    """Algorithmic bytes of one SpMV: the nonzero values (elem each), the
+    column indices of the entries stored with explicit columns (4 bytes,
+    col_frac of the nonzeros; slices with a shared offset list store none),
+    the input vector read once and the output written once (2 n elem).  The
+    zero padding of the sliced layout is not counted."""
+    return elem * nnz + 4 * col_frac * nnz + 2 * n * elem
 
-    Per SpMV: values + column indices (elem + 4 per nonzero), the input
-    vector read once and the output written once (2 n elem).  Epilogue of
-    launch q < s: dinv read and z_{q+1} written (2 n elem), plus z_{q-1} read
-    for q >= 2 (n elem).  Padding of the sliced layout is not counted.
-    """
-    per_spmv = (elem + 4) * nnz + 2 * n * elem
+
+def spmv_family_bytes(n: int, nnz: int, s: int, elem: int, col_frac: float = 1.0) -> float:
+    """Algorithmic bytes of one matrix powers kernel (s SpMV launches): s
+    SpMVs plus the epilogues, dinv read and z_{q+1} written for q < s (2 n
+    elem) and z_{q-1} read for 2 <= q < s (n elem)."""
     epi = sum((2 if q == 1 else 3) * n * elem for q in range(1, s))
-    return s * per_spmv + epi
+    return s * spmv_bytes(n, nnz, elem, col_frac) + epi
+
+
+def csr_family_bytes(n: int, nnz: int, s: int, elem: int) -> float:
+    """The same with a plain CSR stream: 4-byte column index per nonzero and
+    a 4-byte row pointer per row."""
+    return spmv_family_bytes(n, nnz, s, elem, 1.0) + s * 4 * (n + 1)
 
 
 def phase_bytes(n: int, s: int, elem: int) -> dict:
@@ -101,6 +111,10 @@ def main() -> int:
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-profile", action="store_true",
                     help="time without the per-phase HIP events")
+    ap.add_argument("--mode", choices=["solve", "kernels"], default="solve",
+                    help="kernels: a few launches of each hot kernel on the workload and a "
+                         "copy kernel of known size (for rocprofv3 counter passes)")
+    ap.add_argument("--reps", type=int, default=5)
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -123,9 +137,14 @@ def main() -> int:
     t0 = time.time()
     M = P.Matrix.from_csr(A, fp32=not args.no_mixed, device=dev)
     info_m = M.info()
+    col_frac = 1.0 - info_m["shared_slices"] / info_m["slices"]
     log(f"[bench] matrix on device in {time.time() - t0:.1f}s: slots {info_m['slots']} "
-        f"(padding {info_m['slots'] / A.nnz - 1:.4f}), {info_m['device_bytes'] / 1e9:.2f} GB")
+        f"(padding {info_m['slots'] / A.nnz - 1:.4f}), {info_m['shared_slices']} of "
+        f"{info_m['slices']} slices with shared offsets, {info_m['device_bytes'] / 1e9:.2f} GB")
     b = torch.from_numpy(b_np).to(dev)
+    if args.mode == "kernels":
+        print(json.dumps(kernel_pass(P, torch, M, A, b, interval, args, col_frac)), flush=True)
+        return 0
     opts = dict(s=args.s, sweeps=args.sweeps, interval=interval, tol=args.tol,
                 profile=not args.no_profile)
 
@@ -183,13 +202,15 @@ def main() -> int:
         pr = last["profile"]
         sp = pr["spmv"]
         mpk_calls = sp["launches"] / s
-        b_mpk = spmv_family_bytes(n, nnz, s, 8)
+        b_mpk = spmv_family_bytes(n, nnz, s, 8, col_frac)
         achieved = b_mpk * mpk_calls / (sp["ms"] / 1e3) / 1e9
         out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                            "kernel": "k_spmv (matrix powers kernel, FP64)",
                            "avg_launch_us": 1e3 * sp["ms"] / sp["launches"],
-                           "bytes_per_launch": b_mpk / s}
+                           "bytes_per_launch": b_mpk / s,
+                           "csr_equivalent_gbs": csr_family_bytes(n, nnz, s, 8) * mpk_calls
+                           / (sp["ms"] / 1e3) / 1e9}
         pb = phase_bytes(n, s, 8)
         phases = {}
         tot_b, tot_ms = 0.0, 0.0
@@ -224,6 +245,56 @@ def main() -> int:
 
 
 L_PHASES = ["spmv", "gram_update", "gram_rect", "fgs", "norm", "xr"]
+
+COPY_BYTES = 1 << 30   # calibration copy: 1 GiB read + 1 GiB written
+
+
+def kernel_pass(P, torch, M, A, b, interval, args, col_frac):
+    """Launches each hot kernel `reps` times and a plain copy of known size.
+
+    Times each kernel with events on the current stream (the one the library
+    launches on).  Used under rocprofv3 --pmc to relate FETCH_SIZE and
+    WRITE_SIZE to bytes: the copy moves exactly COPY_BYTES each way.
+    """
+    n, s, reps = A.n, args.s, args.reps
+    ld = P.leading_dim(n)
+    src = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device=M.device)
+    dst = torch.empty_like(src)
+    x = torch.randn(n, dtype=torch.float64, device=M.device)
+    Zb = torch.randn((s, ld), dtype=torch.float64, device=M.device)
+    Qb, AZb, AQb = torch.randn_like(Zb), torch.randn_like(Zb), torch.randn_like(Zb)
+    beta = torch.randn((s, s), dtype=torch.float64, device=M.device) * 0.1
+    alpha = torch.randn(s, dtype=torch.float64, device=M.device)
+    r = torch.randn(n, dtype=torch.float64, device=M.device)
+    xr_x = torch.zeros(n, dtype=torch.float64, device=M.device)
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    out = {}
+
+    def timed(name, fn, nbytes):
+        fn()
+        torch.cuda.synchronize()
+        a, z = ev(), ev()
+        a.record()
+        for _ in range(reps):
+            fn()
+        z.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(z) / reps
+        out[name] = {"avg_ms": ms, "bytes": nbytes, "gbs": nbytes / (ms / 1e3) / 1e9}
+        log(f"[kernels] {name}: {ms * 1e3:.1f} us, {out[name]['gbs']:.0f} GB/s")
+
+    timed("copy_1GiB", lambda: dst.copy_(src), 2 * COPY_BYTES)
+    timed("spmv_f64", lambda: P.spmv(M, x), spmv_bytes(n, A.nnz, 8, col_frac))
+    timed("mpk_f64_s%d" % s, lambda: P.mpk(M, r, s, interval, ld=ld),
+          spmv_family_bytes(n, A.nnz, s, 8, col_frac))
+    timed("gram_update", lambda: P.block_update_gram(n, Zb, Qb, AZb, AQb, beta, r),
+          (6 * s + 1) * 8 * n)
+    timed("gram_rect", lambda: P.gram_rect(n, Qb, AZb), 2 * s * 8 * n)
+    timed("xr", lambda: P.xr_update(M, Qb, AQb, alpha, xr_x, r), (2 * s + 6) * 8 * n)
+    if M.fp32:
+        x32 = x.float()
+        timed("spmv_f32", lambda: P.spmv(M, x32), spmv_bytes(n, A.nnz, 4, col_frac))
+    return {"mode": "kernels", "n": n, "nnz": A.nnz, "s": s, "reps": reps, "kernels": out}
 
 if __name__ == "__main__":
     sys.exit(main())

@@ -83,7 +83,8 @@ typedef struct {
     double tol;                 /* stop when ||r|| <= tol ||b|| (recursive r; FP64 true r in MIXED) */
     int32_t max_outer;          /* outer-iteration limit (FP64) / per inner solve limit (MIXED) */
     int32_t precision;          /* sspcg_precision */
-    double inner_tol;           /* MIXED: inner solve stops at ||r_in|| <= inner_tol ||r|| */
+    double inner_tol;           /* MIXED: inner solves reduce their residual by inner_tol, or
+                                   only to half the outer target once that is closer */
     int32_t max_refine;         /* MIXED: limit on FP64 residual corrections */
     int32_t gram;               /* sspcg_gram_solver */
     int32_t check_every;        /* outer iterations enqueued between host polls (>= 1) */
@@ -151,9 +152,12 @@ int sspcg_matrix_create(int32_t n, int32_t nnz, const int32_t* row_ptr, const in
  * order.  Synchronizes `stream`; SSPCG_ERR_BREAKDOWN as for create. */
 int sspcg_matrix_update_values(sspcg_matrix* A, const double* val, sspcg_stream stream);
 int sspcg_matrix_destroy(sspcg_matrix* A);
-/* n, nnz, stored slots of the sliced layout (nnz plus padding), device bytes held. */
+/* Size of the library's copy (host outputs, each may be NULL): n, nnz, the
+ * stored slots of the sliced layout (nnz plus zero padding), the number of
+ * 64-row slices and how many of them use a shared offset list (no column
+ * indices), and the device bytes held. */
 int sspcg_matrix_info(const sspcg_matrix* A, int64_t* n, int64_t* nnz, int64_t* slots,
-                      int64_t* device_bytes);
+                      int64_t* slices, int64_t* shared_slices, int64_t* device_bytes);
 
 /* ---------------------------------------------------------------- solvers */
 /* Workspace (device bytes) that sspcg_solve / sspcg_pcg_solve need. */

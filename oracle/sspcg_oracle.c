@@ -647,7 +647,10 @@ static int inner_sspcg_f32(int64_t n, const int32_t* rp, const int32_t* col,
 }
 
 /* Iterative refinement: r = b - A x in FP64; stop when ||r|| <= tol ||b||;
- * else solve A d = fl32(r) with the FP32 inner method and set x += d.
+ * else solve A d = fl32(r) with the FP32 inner method and set x += d.  The
+ * inner solve of a refinement reduces its residual by inner_tol, or only to
+ * half the outer target when that is less work:
+ * its relative tolerance is min(max(inner_tol, tol / (2 relres)), 1/2).
  * hist (optional, max_refine+1 doubles): true relative residual before each
  * correction.  An inner NOT_CONVERGED is accepted (the correction is still
  * applied); inner breakdowns end the solve. */
@@ -693,9 +696,12 @@ int or_sspcg_mixed(int64_t n, const int32_t* rp, const int32_t* col, const doubl
         if (relres <= tol) { status = OR_OK; break; }
         if (nref >= max_refine) { status = OR_NOT_CONVERGED; break; }
         for (int64_t i = 0; i < n; ++i) r32[i] = (float)r[i];
+        double itol = 0.5 * tol / relres;
+        if (itol < inner_tol) itol = inner_tol;
+        if (itol > 0.5) itol = 0.5;
         int it = 0;
         const int st = inner_sspcg_f32(n, rp, col, val32, dinv32, r32, d32, s, sweeps,
-                                       lmin, lmax, inner_tol, max_inner, &it);
+                                       lmin, lmax, itol, max_inner, &it);
         inner_total += it;
         if (st != OR_OK && st != OR_NOT_CONVERGED) { status = st; break; }
         for (int64_t i = 0; i < n; ++i) x[i] += (double)d32[i];

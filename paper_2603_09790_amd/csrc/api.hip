@@ -521,7 +521,9 @@ int solve_mixed(const sspcg_matrix* A, const double* b, double* x, const sspcg_p
             status = SSPCG_NOT_CONVERGED;
             break;
         }
-        rc = init_ctrl(A, ctrl, std::sqrt(sums[1]), p->inner_tol, p->max_outer, 0.0, st);
+        // reduce by inner_tol, or only to half the outer target when closer
+        const double itol = std::min(std::max(p->inner_tol, 0.5 * p->tol / relres), 0.5);
+        rc = init_ctrl(A, ctrl, std::sqrt(sums[1]), itol, p->max_outer, 0.0, st);
         if (rc == SSPCG_OK) rc = launch_fill<float>(A->n, d, 0.0f, st);
         if (rc == SSPCG_OK) rc = run_sspcg<float>(A, p, w, base, d, A->dinv32, p->max_outer, nullptr, st);
         if (rc != SSPCG_OK) return rc;
@@ -710,35 +712,57 @@ int sspcg_matrix_create(int32_t n, int32_t nnz, const int32_t* row_ptr, const in
         return rc;
     };
     const size_t b_sp = align_up(sizeof(int64_t) * (A->nslices + 1), 256);
+    const size_t b_aux = align_up(sizeof(int64_t) * A->nslices, 256);
     const size_t b_dinv = align_up(sizeof(double) * (size_t)n, 256);
     const size_t b_dinv32 = f32 ? align_up(sizeof(float) * (size_t)n, 256) : 0;
-    const size_t b_small = b_sp + b_dinv + b_dinv32 + 256;
+    const size_t b_small = b_sp + b_aux + b_dinv + b_dinv32 + 256;
     hipError_t e = hipMalloc(&A->mem, b_small);
     if (e != hipSuccess) return fail(hip_fail(e, "hipMalloc(matrix)"));
     char* m = static_cast<char*>(A->mem);
     A->slice_ptr = reinterpret_cast<int64_t*>(m);
-    A->dinv = reinterpret_cast<double*>(m + b_sp);
-    A->dinv32 = f32 ? reinterpret_cast<float*>(m + b_sp + b_dinv) : nullptr;
-    A->dflags = reinterpret_cast<int32_t*>(m + b_sp + b_dinv + b_dinv32);
+    A->slice_aux = reinterpret_cast<int64_t*>(m + b_sp);
+    A->dinv = reinterpret_cast<double*>(m + b_sp + b_aux);
+    A->dinv32 = f32 ? reinterpret_cast<float*>(m + b_sp + b_aux + b_dinv) : nullptr;
+    A->dflags = reinterpret_cast<int32_t*>(m + b_sp + b_aux + b_dinv + b_dinv32);
     e = hipHostMalloc((void**)&A->host_ctrl, 2 * sizeof(Ctrl), hipHostMallocDefault);
     if (e != hipSuccess) return fail(hip_fail(e, "hipHostMalloc"));
-    std::vector<int64_t> sp;
-    int rc = matrix_inspect(A, val, false, &sp, st);
-    if (rc != SSPCG_OK) return fail(rc);
-    A->slots = sp.back();
-    if (A->slots >= ((int64_t)1 << 40)) return fail(arg_error("matrix too large"));
-    const size_t b_col = align_up(sizeof(int32_t) * (size_t)A->slots, 256);
+    LayoutPlan plan;
+    int32_t* d_union = nullptr;
+    int rc = matrix_inspect(A, val, false, &plan, &d_union, st);
+    auto fail_union = [&](int r) {
+        if (d_union) {
+            (void)hipFreeAsync(d_union, st);
+            (void)hipStreamSynchronize(st);
+        }
+        return fail(r);
+    };
+    if (rc != SSPCG_OK) return fail_union(rc);
+    A->slots = plan.slots;
+    A->nshared = plan.nshared;
+    if (A->slots >= ((int64_t)1 << 40)) return fail_union(arg_error("matrix too large"));
+    const size_t b_col = align_up(sizeof(int32_t) * (size_t)plan.ncol, 256);
+    const size_t b_off = align_up(sizeof(int32_t) * (size_t)plan.nsoff, 256);
     const size_t b_val = align_up(sizeof(double) * (size_t)A->slots, 256);
     const size_t b_val32 = f32 ? align_up(sizeof(float) * (size_t)A->slots, 256) : 0;
-    e = hipMalloc(&A->mem_vals, b_col + b_val + b_val32);
-    if (e != hipSuccess) return fail(hip_fail(e, "hipMalloc(matrix values)"));
+    e = hipMalloc(&A->mem_vals, b_col + b_off + b_val + b_val32);
+    if (e != hipSuccess) return fail_union(hip_fail(e, "hipMalloc(matrix values)"));
     char* mv = static_cast<char*>(A->mem_vals);
     A->scol = reinterpret_cast<int32_t*>(mv);
-    A->sval = reinterpret_cast<double*>(mv + b_col);
-    A->sval32 = f32 ? reinterpret_cast<float*>(mv + b_col + b_val) : nullptr;
-    A->mem_bytes = b_small + b_col + b_val + b_val32;
-    e = hipMemcpyAsync(A->slice_ptr, sp.data(), sizeof(int64_t) * sp.size(), hipMemcpyHostToDevice, st);
-    if (e != hipSuccess) return fail(hip_fail(e, "slice offsets"));
+    A->soff = reinterpret_cast<int32_t*>(mv + b_col);
+    A->sval = reinterpret_cast<double*>(mv + b_col + b_off);
+    A->sval32 = f32 ? reinterpret_cast<float*>(mv + b_col + b_off + b_val) : nullptr;
+    A->mem_bytes = b_small + b_col + b_off + b_val + b_val32;
+    e = hipMemcpyAsync(A->slice_ptr, plan.slice_ptr.data(), sizeof(int64_t) * plan.slice_ptr.size(),
+                       hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(A->slice_aux, plan.slice_aux.data(),
+                           sizeof(int64_t) * plan.slice_aux.size(), hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return fail_union(hip_fail(e, "slice offsets"));
+    rc = matrix_pack(A, d_union, st);
+    if (rc != SSPCG_OK) return fail_union(rc);
+    e = hipFreeAsync(d_union, st);
+    d_union = nullptr;
+    if (e != hipSuccess) return fail(hip_fail(e, "hipFreeAsync"));
     rc = matrix_fill(A, val, false, st);
     if (rc != SSPCG_OK) return fail(rc);
     *out = A;
@@ -752,7 +776,7 @@ int sspcg_matrix_update_values(sspcg_matrix* A, const double* val, sspcg_stream 
     RETURN_IF(check_matrix(A));
     if (!val || !aligned(val, 8)) return arg_error("val is NULL or misaligned");
     hipStream_t st = as_stream(stream);
-    RETURN_IF(matrix_inspect(A, val, true, nullptr, st));
+    RETURN_IF(matrix_inspect(A, val, true, nullptr, nullptr, st));
     return matrix_fill(A, val, true, st);
     API_CATCH
 }
@@ -770,12 +794,14 @@ int sspcg_matrix_destroy(sspcg_matrix* A)
 }
 
 int sspcg_matrix_info(const sspcg_matrix* A, int64_t* n, int64_t* nnz, int64_t* slots,
-                      int64_t* device_bytes)
+                      int64_t* slices, int64_t* shared_slices, int64_t* device_bytes)
 {
     RETURN_IF(check_matrix(A));
     if (n) *n = A->n;
     if (nnz) *nnz = A->nnz;
     if (slots) *slots = A->slots;
+    if (slices) *slices = A->nslices;
+    if (shared_slices) *shared_slices = A->nshared;
     if (device_bytes) *device_bytes = (int64_t)A->mem_bytes;
     return SSPCG_OK;
 }

@@ -36,18 +36,32 @@ struct Ctrl {
 };
 static_assert(sizeof(Ctrl) == 128, "Ctrl layout");
 
-// Sliced layout of a CSR matrix: slice c holds rows 64c..64c+63; entry k of
-// lane l sits at slice_ptr[c] + 64k + l; each slice is padded to its
-// longest row with value 0 and column = the row itself.
+// Sliced layout of a CSR matrix: slice c holds rows 64c..64c+63, one per
+// lane; entry k of lane l sits at slot slice_ptr[c] + 64k + l.  Two kinds of
+// slice:
+//  - shared offsets (slice_aux[c] < 0): the slice's rows draw their columns
+//    from one sorted list of offsets o_k = col - row, stored once at
+//    soff[-slice_aux[c] - 1 + k]; entry k of a row is its value at column
+//    row + o_k, or 0 where the row has no such entry.  This is the case for
+//    stencil matrices and removes the column indices from the stream.
+//  - explicit columns (slice_aux[c] >= 0): entry k holds the row's k-th
+//    stored entry, its column at col[slice_aux[c] + 64k + l]; rows are padded
+//    to the slice's longest row with value 0 and the row as column.
+// Either way the entries of a row keep the CSR order.
 template <typename T>
 struct Sell {
     int32_t n;
     int64_t nslices;
-    const int64_t* slice_ptr;   // nslices + 1 offsets, multiples of 64
-    const int32_t* col;
+    const int64_t* slice_ptr;   // nslices + 1 slot offsets, multiples of 64
+    const int64_t* slice_aux;   // kind and offset of each slice, see above
+    const int32_t* col;         // explicit column indices
+    const int32_t* soff;        // shared offset lists
     const T* val;
     const T* dinv;              // 1 / diag(A)
 };
+
+// Longest shared offset list a slice may use.
+constexpr int kMaxUnion = 64;
 
 // Grid of a persistent row kernel: a multiple of kNumXcd blocks.
 int persistent_grid(int64_t ntiles, int blocks_per_cu);

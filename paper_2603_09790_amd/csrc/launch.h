@@ -9,16 +9,18 @@ struct sspcg_matrix {
     int32_t n = 0, nnz = 0, flags = 0, device = 0;
     const int32_t* row_ptr = nullptr;   // caller's CSR (device, not owned)
     const int32_t* col = nullptr;
-    int64_t nslices = 0, slots = 0;
+    int64_t nslices = 0, slots = 0, nshared = 0;
     int64_t* slice_ptr = nullptr;       // owned (inside `mem`)
-    int32_t* scol = nullptr;
+    int64_t* slice_aux = nullptr;       // owned (inside `mem`)
+    int32_t* scol = nullptr;            // owned (inside `mem_vals`)
+    int32_t* soff = nullptr;            // owned (inside `mem_vals`)
     double* sval = nullptr;
     float* sval32 = nullptr;
     double* dinv = nullptr;
     float* dinv32 = nullptr;
     int32_t* dflags = nullptr;
-    void* mem = nullptr;                // device allocation: slice_ptr, dinv, dinv32, dflags
-    void* mem_vals = nullptr;           // device allocation: scol, sval, sval32
+    void* mem = nullptr;                // device allocation: slice_ptr/aux, dinv, dinv32, dflags
+    void* mem_vals = nullptr;           // device allocation: scol, soff, sval, sval32
     size_t mem_bytes = 0;
     sspcg::Ctrl* host_ctrl = nullptr;   // pinned mirror for polling (2 entries)
     sspcg_profile profile{};            // last profiled solve
@@ -29,10 +31,18 @@ namespace sspcg {
 template <typename T>
 Sell<T> sell_view(const sspcg_matrix* A);
 
-// Matrix layout (sell.hip).  inspect validates the CSR input on the device,
-// writes dinv and returns the slice offsets; fill writes the sliced arrays.
-int matrix_inspect(sspcg_matrix* A, const double* val, bool values_only,
-                   std::vector<int64_t>* slice_ptr, hipStream_t st);
+// Matrix layout (sell.hip).  inspect validates the CSR input on the device
+// and writes dinv; with a plan it also chooses the kind of every slice (the
+// per-slice offset unions stay in *d_union, nslices x kMaxUnion, for
+// matrix_pack).  pack copies the chosen offset lists; fill writes the
+// sliced values (and explicit columns).
+struct LayoutPlan {
+    std::vector<int64_t> slice_ptr, slice_aux;
+    int64_t slots = 0, ncol = 0, nsoff = 0, nshared = 0;
+};
+int matrix_inspect(sspcg_matrix* A, const double* val, bool values_only, LayoutPlan* plan,
+                   int32_t** d_union, hipStream_t st);
+int matrix_pack(sspcg_matrix* A, const int32_t* d_union, hipStream_t st);
 int matrix_fill(sspcg_matrix* A, const double* val, bool values_only, hipStream_t st);
 template <typename T>
 int launch_mpk_start(int64_t n, const T* r, const T* dinv, T* z1, T* p1, hipStream_t st);

@@ -3,15 +3,20 @@
 // SpMV of classical PCG.
 //
 // Layout.  Slice c holds rows 64c..64c+63, one per lane of a wavefront.
-// Entry k of every row in the slice is stored contiguously (64 values, then
-// 64 column indices), so each load instruction of the wave reads 512 bytes
-// of values and 256 bytes of indices with no gaps.  A slice is padded to its
-// longest row; a padding slot has value 0 and the row itself as column, so
-// it adds an exact zero and gathers a value the row needs anyway.  For the
-// 27-point stencil on 192^3 the padding is 0.4% of the nonzeros.  The
-// entries of a row keep their CSR order, which is the summation order.
+// Entry k of every row in the slice is stored contiguously (64 values), so
+// each load instruction of the wave reads 512 contiguous bytes of values.
+// In a stencil matrix the rows of a slice use the same column offsets
+// col - row; such a slice stores its sorted offset list once and no column
+// indices at all (8 instead of 12 bytes per FP64 entry, 4 instead of 8 in
+// FP32), and the gathers x[row + o_k] of a wave are contiguous too.  A row
+// without an entry at offset o_k holds an exact zero there and gathers its
+// own element instead.  Slices whose offset union is too long keep explicit
+// columns (64 indices per entry k), padded to the longest row.  In both
+// kinds the entries of a row keep their CSR order, which is the summation
+// order, and a zero adds nothing: the sum is the CSR sum.
 
 #include <algorithm>
+#include <climits>
 #include <vector>
 
 #include "launch.h"
@@ -71,11 +76,75 @@ __global__ __launch_bounds__(kRowBlock) void k_inspect(int32_t n, int32_t nnz, i
     }
 }
 
+__device__ inline int wave_min(int v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = min(v, __shfl_xor(v, off, kWave));
+    return v;
+}
+
+// One wavefront per slice: the sorted union of the offsets col - row of the
+// slice's rows (a merge of 64 sorted lists), or -1 in ulen when the union
+// exceeds kMaxUnion or a row's columns are not strictly increasing.
+__global__ __launch_bounds__(kRowBlock) void k_slice_union(int32_t n, int64_t nslices,
+                                                           const int32_t* __restrict__ rp,
+                                                           const int32_t* __restrict__ col,
+                                                           int32_t* __restrict__ uni,
+                                                           int32_t* __restrict__ ulen)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t c = (int64_t)blockIdx.x * (kRowBlock / kWave) + threadIdx.x / kWave;
+    if (c >= nslices) return;
+    const int64_t row = c * kSlice + lane;
+    int32_t p = 0, e = 0;
+    if (row < n) {
+        p = rp[row];
+        e = rp[row + 1];
+    }
+    bool sorted = true;
+    int prev = INT_MIN;
+    int U = 0;
+    for (;;) {
+        const int cur = p < e ? col[p] - (int32_t)row : INT_MAX;
+        const int m = wave_min(cur);
+        if (m == INT_MAX) break;
+        if (U < kMaxUnion && lane == 0) uni[c * kMaxUnion + U] = m;
+        ++U;
+        if (p < e && cur == m) {
+            if (cur <= prev) sorted = false;
+            prev = cur;
+            ++p;
+        }
+        if (U > kMaxUnion) break;
+    }
+    const bool all_sorted = __all(sorted);
+    if (lane == 0) ulen[c] = (U > kMaxUnion || !all_sorted) ? -1 : U;
+}
+
+// Copies the offset lists of the shared-offset slices into soff.
+__global__ __launch_bounds__(kRowBlock) void k_pack_union(int64_t nslices,
+                                                          const int64_t* __restrict__ slice_ptr,
+                                                          const int64_t* __restrict__ slice_aux,
+                                                          const int32_t* __restrict__ uni,
+                                                          int32_t* __restrict__ soff)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t c = (int64_t)blockIdx.x * (kRowBlock / kWave) + threadIdx.x / kWave;
+    if (c >= nslices) return;
+    const int64_t aux = slice_aux[c];
+    if (aux >= 0) return;
+    const int w = (int)((slice_ptr[c + 1] - slice_ptr[c]) / kSlice);
+    for (int k = lane; k < w; k += kWave) soff[-aux - 1 + k] = uni[c * kMaxUnion + k];
+}
+
+// One thread per row: values (and explicit columns) of the sliced layout.
 __global__ __launch_bounds__(kRowBlock) void k_fill(int32_t n, int64_t nslices,
                                                     const int32_t* __restrict__ rp,
                                                     const int32_t* __restrict__ col,
                                                     const double* __restrict__ val,
                                                     const int64_t* __restrict__ slice_ptr,
+                                                    const int64_t* __restrict__ slice_aux,
+                                                    const int32_t* __restrict__ soff,
                                                     int32_t* __restrict__ scol,
                                                     double* __restrict__ sval,
                                                     float* __restrict__ sval32, bool values_only)
@@ -84,24 +153,39 @@ __global__ __launch_bounds__(kRowBlock) void k_fill(int32_t n, int64_t nslices,
     const int64_t c = i / kSlice;
     if (c >= nslices) return;
     const int lane = (int)(i % kSlice);
-    const int64_t base = slice_ptr[c];
+    const int64_t base = slice_ptr[c], aux = slice_aux[c];
     const int w = (int)((slice_ptr[c + 1] - base) / kSlice);
     int32_t a = 0, len = 0;
     if (i < n) {
         a = rp[i];
         len = rp[i + 1] - a;
     }
-    for (int k = 0; k < w; ++k) {
-        const int64_t slot = base + (int64_t)k * kSlice + lane;
-        double v = 0.0;
-        int32_t cc = i < n ? (int32_t)i : 0;
-        if (k < len) {
-            v = val[a + k];
-            cc = col[a + k];
+    if (aux < 0) {
+        const int32_t* off = soff + (-aux - 1);
+        int32_t p = 0;
+        for (int k = 0; k < w; ++k) {
+            double v = 0.0;
+            if (p < len && col[a + p] - (int32_t)i == off[k]) {
+                v = val[a + p];
+                ++p;
+            }
+            const int64_t slot = base + (int64_t)k * kSlice + lane;
+            sval[slot] = v;
+            if (sval32) sval32[slot] = (float)v;
         }
-        sval[slot] = v;
-        if (sval32) sval32[slot] = (float)v;
-        if (!values_only) scol[slot] = cc;
+    } else {
+        for (int k = 0; k < w; ++k) {
+            const int64_t slot = base + (int64_t)k * kSlice + lane;
+            double v = 0.0;
+            int32_t cc = i < n ? (int32_t)i : 0;
+            if (k < len) {
+                v = val[a + k];
+                cc = col[a + k];
+            }
+            sval[slot] = v;
+            if (sval32) sval32[slot] = (float)v;
+            if (!values_only) scol[aux + (int64_t)k * kSlice + lane] = cc;
+        }
     }
 }
 
@@ -113,11 +197,11 @@ __device__ inline T ld_stream(const T* p)
     return __builtin_nontemporal_load(p);
 }
 
-// Sum of one row of the sliced layout, entries in CSR order.  FP32 values
-// and vectors are multiplied exactly in FP64 and summed in FP64.
+// Sum of one row of an explicit-column slice, entries in CSR order.  FP32
+// values and vectors are multiplied exactly in FP64 and summed in FP64.
 template <typename T, int U>
-__device__ inline double sell_row(const int32_t* __restrict__ cp, const T* __restrict__ vp, int w,
-                                  const T* __restrict__ x)
+__device__ inline double row_explicit(const int32_t* __restrict__ cp, const T* __restrict__ vp, int w,
+                                      const T* __restrict__ x)
 {
     double acc = 0.0;
     int k = 0;
@@ -141,7 +225,46 @@ __device__ inline double sell_row(const int32_t* __restrict__ cp, const T* __res
     return acc;
 }
 
+// Sum of one row of a shared-offset slice: entry k multiplies x[row + o_k],
+// or x[self] (an exact zero term) where the row has no entry at o_k.
+template <typename T, int U>
+__device__ inline double row_shared(const int32_t* __restrict__ off, const T* __restrict__ vp, int w,
+                                    int32_t row, int32_t self, const T* __restrict__ x)
+{
+    double acc = 0.0;
+    int k = 0;
+    for (; k + U <= w; k += U) {
+        T vv[U], xx[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) vv[u] = ld_stream(vp + (int64_t)(k + u) * kSlice);
+#pragma unroll
+        for (int u = 0; u < U; ++u) xx[u] = x[vv[u] != T(0) ? row + off[k + u] : self];
+#pragma unroll
+        for (int u = 0; u < U; ++u) acc = fma((double)vv[u], (double)xx[u], acc);
+    }
+    for (; k < w; ++k) {
+        const T vv = ld_stream(vp + (int64_t)k * kSlice);
+        acc = fma((double)vv, (double)x[vv != T(0) ? row + off[k] : self], acc);
+    }
+    return acc;
+}
+
 constexpr int kUnroll = 9;
+
+// (A x)_row for the row of this lane in slice c (c < nslices).
+template <typename T>
+__device__ inline double slice_row(const Sell<T>& A, int64_t c, int lane, const T* __restrict__ x)
+{
+    const int64_t base = A.slice_ptr[c], aux = A.slice_aux[c];
+    const int w = (int)((A.slice_ptr[c + 1] - base) / kSlice);
+    const int64_t row = c * kSlice + lane;
+    if (aux < 0) {
+        const int32_t self = (int32_t)(row < A.n ? row : A.n - 1);
+        return row_shared<T, kUnroll>(A.soff + (-aux - 1), A.val + base + lane, w, (int32_t)row,
+                                      self, x);
+    }
+    return row_explicit<T, kUnroll>(A.col + aux + lane, A.val + base + lane, w, x);
+}
 
 template <typename T, int MODE>
 __global__ __launch_bounds__(kRowBlock) void k_spmv(Sell<T> A, const T* __restrict__ x,
@@ -158,9 +281,7 @@ __global__ __launch_bounds__(kRowBlock) void k_spmv(Sell<T> A, const T* __restri
     for (int64_t t = tr.first; t < tr.end; t += tr.step) {
         const int64_t c = t * kSlicesPerTile + wave;
         if (c >= A.nslices) break;
-        const int64_t base = A.slice_ptr[c];
-        const int w = (int)((A.slice_ptr[c + 1] - base) / kSlice);
-        const double acc = sell_row<T, kUnroll>(A.col + base + lane, A.val + base + lane, w, x);
+        const double acc = slice_row<T>(A, c, lane, x);
         const int64_t row = c * kSlice + lane;
         if (row < A.n) {
             const T p = (T)acc;
@@ -190,9 +311,7 @@ __global__ __launch_bounds__(kRowBlock) void k_residual(Sell<double> A, const do
     for (int64_t t = tr.first; t < tr.end; t += tr.step) {
         const int64_t c = t * kSlicesPerTile + wave;
         if (c >= A.nslices) break;
-        const int64_t base = A.slice_ptr[c];
-        const int w = (int)((A.slice_ptr[c + 1] - base) / kSlice);
-        const double ax = sell_row<double, kUnroll>(A.col + base + lane, A.val + base + lane, w, x);
+        const double ax = slice_row<double>(A, c, lane, x);
         const int64_t row = c * kSlice + lane;
         if (row < A.n) {
             const double bi = b[row];
@@ -226,9 +345,7 @@ __global__ __launch_bounds__(kRowBlock) void k_pcg_spmv(Sell<double> A, const do
     for (int64_t t = tr.first; t < tr.end; t += tr.step) {
         const int64_t c = t * kSlicesPerTile + wave;
         if (c >= A.nslices) break;
-        const int64_t base = A.slice_ptr[c];
-        const int w = (int)((A.slice_ptr[c + 1] - base) / kSlice);
-        const double ap = sell_row<double, kUnroll>(A.col + base + lane, A.val + base + lane, w, p);
+        const double ap = slice_row<double>(A, c, lane, p);
         const int64_t row = c * kSlice + lane;
         if (row < A.n) {
             q[row] = ap;
@@ -372,13 +489,13 @@ Sell<T> sell_view(const sspcg_matrix* A);
 template <>
 Sell<double> sell_view<double>(const sspcg_matrix* A)
 {
-    return {A->n, A->nslices, A->slice_ptr, A->scol, A->sval, A->dinv};
+    return {A->n, A->nslices, A->slice_ptr, A->slice_aux, A->scol, A->soff, A->sval, A->dinv};
 }
 
 template <>
 Sell<float> sell_view<float>(const sspcg_matrix* A)
 {
-    return {A->n, A->nslices, A->slice_ptr, A->scol, A->sval32, A->dinv32};
+    return {A->n, A->nslices, A->slice_ptr, A->slice_aux, A->scol, A->soff, A->sval32, A->dinv32};
 }
 
 static int spmv_grid(const sspcg_matrix* A)
@@ -387,13 +504,14 @@ static int spmv_grid(const sspcg_matrix* A)
     return persistent_grid(ntiles, 8);
 }
 
-int matrix_inspect(sspcg_matrix* A, const double* val, bool values_only,
-                   std::vector<int64_t>* slice_ptr, hipStream_t st)
+int matrix_inspect(sspcg_matrix* A, const double* val, bool values_only, LayoutPlan* plan,
+                   int32_t** d_union, hipStream_t st)
 {
     const int64_t nrows_padded = A->nslices * kSlice;
     const int blocks = (int)((nrows_padded + kRowBlock - 1) / kRowBlock);
-    std::vector<int32_t> width(A->nslices);
+    std::vector<int32_t> width(A->nslices), ulen(A->nslices);
     int32_t* dwidth = nullptr;
+    int32_t* dulen = nullptr;
     SSPCG_HIP(hipMallocAsync((void**)&dwidth, sizeof(int32_t) * A->nslices, st));
     SSPCG_HIP(hipMemsetAsync(A->dflags, 0, sizeof(int32_t), st));
     hipLaunchKernelGGL(k_inspect, dim3(blocks), dim3(kRowBlock), 0, st, A->n, A->nnz, A->nslices,
@@ -417,11 +535,46 @@ int matrix_inspect(sspcg_matrix* A, const double* val, bool values_only,
         set_error("a diagonal entry is missing or not positive: A is not SPD");
         return SSPCG_ERR_BREAKDOWN;
     }
-    if (slice_ptr) {
-        slice_ptr->assign(A->nslices + 1, 0);
-        for (int64_t c = 0; c < A->nslices; ++c)
-            (*slice_ptr)[c + 1] = (*slice_ptr)[c] + (int64_t)width[c] * kSlice;
+    if (!plan) return SSPCG_OK;
+    // the pattern is valid: choose the kind of every slice
+    SSPCG_HIP(hipMallocAsync((void**)d_union, sizeof(int32_t) * A->nslices * kMaxUnion, st));
+    SSPCG_HIP(hipMallocAsync((void**)&dulen, sizeof(int32_t) * A->nslices, st));
+    hipLaunchKernelGGL(k_slice_union, dim3(blocks), dim3(kRowBlock), 0, st, A->n, A->nslices,
+                       A->row_ptr, A->col, *d_union, dulen);
+    SSPCG_LAUNCHED("k_slice_union");
+    SSPCG_HIP(hipMemcpyAsync(ulen.data(), dulen, sizeof(int32_t) * A->nslices,
+                             hipMemcpyDeviceToHost, st));
+    SSPCG_HIP(hipFreeAsync(dulen, st));
+    SSPCG_HIP(hipStreamSynchronize(st));
+    plan->slice_ptr.assign(A->nslices + 1, 0);
+    plan->slice_aux.assign(A->nslices, 0);
+    plan->ncol = plan->nsoff = plan->nshared = 0;
+    for (int64_t c = 0; c < A->nslices; ++c) {
+        // shared offsets pay off while the value stream grows by less than
+        // the column stream it removes: 8 U < 12 w bytes per lane (FP64)
+        const bool shared = ulen[c] > 0 && 2 * ulen[c] < 3 * width[c] + 2;
+        int64_t w = width[c];
+        if (shared) {
+            w = ulen[c];
+            plan->slice_aux[c] = -(plan->nsoff + 1);
+            plan->nsoff += w;
+            plan->nshared += 1;
+        } else {
+            plan->slice_aux[c] = plan->ncol;
+            plan->ncol += w * kSlice;
+        }
+        plan->slice_ptr[c + 1] = plan->slice_ptr[c] + w * kSlice;
     }
+    plan->slots = plan->slice_ptr[A->nslices];
+    return SSPCG_OK;
+}
+
+int matrix_pack(sspcg_matrix* A, const int32_t* d_union, hipStream_t st)
+{
+    const int blocks = (int)((A->nslices * kSlice + kRowBlock - 1) / kRowBlock);
+    hipLaunchKernelGGL(k_pack_union, dim3(blocks), dim3(kRowBlock), 0, st, A->nslices,
+                       A->slice_ptr, A->slice_aux, d_union, A->soff);
+    SSPCG_LAUNCHED("k_pack_union");
     return SSPCG_OK;
 }
 
@@ -430,7 +583,8 @@ int matrix_fill(sspcg_matrix* A, const double* val, bool values_only, hipStream_
     const int64_t nrows_padded = A->nslices * kSlice;
     const int blocks = (int)((nrows_padded + kRowBlock - 1) / kRowBlock);
     hipLaunchKernelGGL(k_fill, dim3(blocks), dim3(kRowBlock), 0, st, A->n, A->nslices, A->row_ptr,
-                       A->col, val, A->slice_ptr, A->scol, A->sval, A->sval32, values_only);
+                       A->col, val, A->slice_ptr, A->slice_aux, A->soff, A->scol, A->sval,
+                       A->sval32, values_only);
     SSPCG_LAUNCHED("k_fill");
     SSPCG_HIP(hipStreamSynchronize(st));
     return SSPCG_OK;

@@ -92,11 +92,11 @@ class Matrix:
         self.values_tag = tag
 
     def info(self) -> dict:
-        n, nnz, slots, nbytes = (ctypes.c_int64() for _ in range(4))
-        L.check(L.lib().sspcg_matrix_info(self.handle, ctypes.byref(n), ctypes.byref(nnz),
-                                          ctypes.byref(slots), ctypes.byref(nbytes)),
+        v = [ctypes.c_int64() for _ in range(6)]
+        L.check(L.lib().sspcg_matrix_info(self.handle, *[ctypes.byref(t) for t in v]),
                 "sspcg_matrix_info")
-        return dict(n=n.value, nnz=nnz.value, slots=slots.value, device_bytes=nbytes.value)
+        keys = ("n", "nnz", "slots", "slices", "shared_slices", "device_bytes")
+        return {k: t.value for k, t in zip(keys, v)}
 
     def workspace(self, nbytes: int) -> torch.Tensor:
         if self._work is None or self._work.numel() < nbytes:

@@ -312,3 +312,62 @@ def test_matrix_create_rejects_bad_input():
     with pytest.raises(P.SSPCGError) as e:
         P.Matrix(A.row_ptr, A.col, nanv, device=DEV)
     assert e.value.status == P.ERR_NONFINITE
+
+
+def random_spd_csr(n=1500, per_row=9, seed=21, unsorted=False):
+    """Symmetric, strictly diagonally dominant matrix with a random pattern
+    (its slices need explicit column indices)."""
+    import scipy.sparse as sp
+    rng = np.random.default_rng(seed)
+    rows = np.repeat(np.arange(n), per_row)
+    cols = rng.integers(0, n, size=n * per_row)
+    vals = -rng.uniform(0.1, 1.0, size=n * per_row)
+    M = sp.coo_matrix((vals, (rows, cols)), shape=(n, n)).tocsr()
+    M = M + M.T
+    M.setdiag(0.0)
+    M.eliminate_zeros()
+    d = np.asarray(abs(M).sum(axis=1)).ravel() + rng.uniform(0.5, 2.0, n)
+    M = (M + sp.diags(d)).tocsr()
+    M.sort_indices()
+    rp, col, val = M.indptr.astype(np.int32), M.indices.astype(np.int32), M.data.copy()
+    if unsorted:
+        for i in range(n):
+            a, b = rp[i], rp[i + 1]
+            perm = rng.permutation(b - a)
+            col[a:b] = col[a:b][perm]
+            val[a:b] = val[a:b][perm]
+    return si.CSR(n, rp, col, val, (1, 1, n))
+
+
+@pytest.mark.parametrize("unsorted", [False, True])
+def test_explicit_column_slices(unsorted):
+    A = random_spd_csr(unsorted=unsorted)
+    M = P.Matrix.from_csr(A, fp32=True, device=DEV)
+    assert M.info()["slots"] >= A.nnz
+    x = np.random.default_rng(22).normal(size=A.n)
+    y = host(P.spmv(M, gpu(x)))
+    ref = oracle.spmv(A, x)
+    assert np.abs(y - ref).max() <= 1e-14 * np.abs(ref).max()
+    x32 = x.astype(np.float32)
+    assert np.array_equal(host(P.spmv(M, gpu(x32))),
+                          oracle.spmv_f32(A, A.val.astype(np.float32), x32))
+    b = si.rhs_uniform(A.n)
+    dinv = oracle.jacobi_inverse(A)
+    Dh = np.sqrt(dinv)
+    ev = np.linalg.eigvalsh(si.to_scipy(A).toarray() * np.outer(Dh, Dh))
+    x_g, info = P.solve(M, gpu(b), s=4, sweeps=3, interval=(ev[0], ev[-1]), tol=1e-12)
+    x_o, ro = oracle.sspcg(A, b, s=4, sweeps=3, interval=(ev[0], ev[-1]), tol=1e-12)
+    assert info["status"] == ro["status"] == 0
+    assert np.linalg.norm(host(x_g) - x_o) <= 1e-10 * np.linalg.norm(x_o)
+
+
+def test_stencil_slices_use_shared_offsets():
+    """A stencil matrix stores one offset list per slice: slots ~ stencil size x rows."""
+    N = 32
+    A = si.stencil("27pt", N, si.coeff_blocks(N))
+    M = P.Matrix.from_csr(A, device=DEV)
+    info = M.info()
+    assert info["slots"] == 27 * N**3      # every row padded to the 27 offsets
+    assert info["shared_slices"] == info["slices"] == N**3 // 64
+    # values only: 8 bytes per slot plus small metadata, no column indices
+    assert info["device_bytes"] < 8 * info["slots"] + 40 * A.n
