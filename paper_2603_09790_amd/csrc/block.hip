@@ -174,6 +174,15 @@ int row_grid(int64_t n)
     return persistent_grid((n + kRowBlock - 1) / kRowBlock, 4);
 }
 
+// Persistent grid of a block kernel: up to 8 workgroups per CU, no more than
+// fit at once.
+template <typename K>
+static int block_grid(int64_t n, K kernel)
+{
+    const int resident = resident_blocks(reinterpret_cast<const void*>(kernel), kRowBlock);
+    return persistent_grid((n + kRowBlock - 1) / kRowBlock, 8, resident);
+}
+
 #define SSPCG_S_CASES(X) \
     X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16)
 
@@ -182,16 +191,19 @@ int launch_update_gram(int64_t n, int s, const T* Z, T* Q, const T* AZ, T* AQ, c
                        const T* r, int64_t ld, double* partials, int* G_out, const Ctrl* ctrl,
                        hipStream_t st)
 {
-    const int G = row_grid(n);
+    int G = 0;
     switch (s) {
 #define X(S)                                                                                     \
     case S:                                                                                      \
-        if (beta)                                                                                \
+        if (beta) {                                                                              \
+            G = block_grid(n, k_update_gram<S, T, false>);                                       \
             hipLaunchKernelGGL((k_update_gram<S, T, false>), dim3(G), dim3(kRowBlock), 0, st, n, \
                                ld, Z, Q, AZ, AQ, beta, r, partials, ctrl);                       \
-        else                                                                                     \
+        } else {                                                                                 \
+            G = block_grid(n, k_update_gram<S, T, true>);                                        \
             hipLaunchKernelGGL((k_update_gram<S, T, true>), dim3(G), dim3(kRowBlock), 0, st, n,  \
                                ld, Z, Q, AZ, AQ, beta, r, partials, ctrl);                       \
+        }                                                                                        \
         break;
         SSPCG_S_CASES(X)
 #undef X
@@ -208,10 +220,11 @@ template <typename T>
 int launch_gram_rect(int64_t n, int s, const T* Q, const T* AZ, int64_t ld, double* partials,
                      int* G_out, const Ctrl* ctrl, hipStream_t st)
 {
-    const int G = row_grid(n);
+    int G = 0;
     switch (s) {
 #define X(S)                                                                                    \
     case S:                                                                                     \
+        G = block_grid(n, k_gram_rect<S, T>);                                                   \
         hipLaunchKernelGGL((k_gram_rect<S, T>), dim3(G), dim3(kRowBlock), 0, st, n, ld, Q, AZ, \
                            partials, ctrl);                                                     \
         break;
@@ -231,10 +244,11 @@ int launch_xr(int64_t n, int s, const T* Q, const T* AQ, const double* alpha, in
               T* r, const T* dinv, T* z1, double* partials, int* G_out, const Ctrl* ctrl,
               hipStream_t st)
 {
-    const int G = row_grid(n);
+    int G = 0;
     switch (s) {
 #define X(S)                                                                                   \
     case S:                                                                                    \
+        G = block_grid(n, k_xr<S, T>);                                                         \
         hipLaunchKernelGGL((k_xr<S, T>), dim3(G), dim3(kRowBlock), 0, st, n, ld, Q, AQ, alpha, \
                            x, r, dinv, z1, partials, ctrl);                                    \
         break;

@@ -63,9 +63,14 @@ struct Sell {
 // Longest shared offset list a slice may use.
 constexpr int kMaxUnion = 64;
 
-// Grid of a persistent row kernel: a multiple of kNumXcd blocks.
-int persistent_grid(int64_t ntiles, int blocks_per_cu);
+// Grid of a persistent row kernel: at most `blocks_per_cu` workgroups per CU
+// and never more than fit at once (`resident`, from the occupancy of the
+// kernel), so no workgroup waits for another to finish its tile list; a
+// multiple of kNumXcd blocks.
+int persistent_grid(int64_t ntiles, int blocks_per_cu, int resident = 1 << 20);
 int num_cus();
+// Workgroups of `kernel` (256 threads) that fit on one CU at once.
+int resident_blocks(const void* kernel, int threads);
 
 // Error plumbing for the C ABI.
 void set_error(const std::string& msg);
@@ -99,6 +104,17 @@ __device__ inline TileRange xcd_tiles(int64_t ntiles)
         return {lo + j, hi, per};
     }
     return {b, ntiles, G};
+}
+
+// Tile of a non-persistent launch (one tile per workgroup, grid = ntiles):
+// the first 8*floor(ntiles/8) tiles are split into 8 contiguous ranges, one
+// per die, walked in dispatch order; the remaining tiles map to themselves.
+__device__ inline int64_t xcd_block_tile()
+{
+    const int64_t b = blockIdx.x, G = gridDim.x;
+    const int64_t full = G / kNumXcd * kNumXcd;
+    if (b >= full) return b;
+    return (b % kNumXcd) * (full / kNumXcd) + b / kNumXcd;
 }
 
 __device__ inline double wave_sum(double v)

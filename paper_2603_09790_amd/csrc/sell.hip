@@ -17,6 +17,8 @@
 
 #include <algorithm>
 #include <climits>
+#include <mutex>
+#include <unordered_map>
 #include <vector>
 
 #include "launch.h"
@@ -276,22 +278,19 @@ __global__ __launch_bounds__(kRowBlock) void k_spmv(Sell<T> A, const T* __restri
     if (ctrl && ctrl->done) return;
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
     constexpr int kSlicesPerTile = kRowBlock / kSlice;
-    const int64_t ntiles = (A.nslices + kSlicesPerTile - 1) / kSlicesPerTile;
-    const TileRange tr = xcd_tiles(ntiles);
-    for (int64_t t = tr.first; t < tr.end; t += tr.step) {
-        const int64_t c = t * kSlicesPerTile + wave;
-        if (c >= A.nslices) break;
-        const double acc = slice_row<T>(A, c, lane, x);
-        const int64_t row = c * kSlice + lane;
-        if (row < A.n) {
-            const T p = (T)acc;
-            y[row] = p;
-            if (MODE >= 1) {
-                const double t1 = (double)A.dinv[row] * (double)p;
-                double z = c1 * t1 - c2 * (double)x[row];
-                if (MODE == 2) z -= c3 * (double)zprev[row];
-                znext[row] = (T)z;
-            }
+    // one tile (4 slices, one per wavefront) per workgroup
+    const int64_t c = xcd_block_tile() * kSlicesPerTile + wave;
+    if (c >= A.nslices) return;
+    const double acc = slice_row<T>(A, c, lane, x);
+    const int64_t row = c * kSlice + lane;
+    if (row < A.n) {
+        const T p = (T)acc;
+        y[row] = p;
+        if (MODE >= 1) {
+            const double t1 = (double)A.dinv[row] * (double)p;
+            double z = c1 * t1 - c2 * (double)x[row];
+            if (MODE == 2) z -= c3 * (double)zprev[row];
+            znext[row] = (T)z;
         }
     }
 }
@@ -474,9 +473,23 @@ int num_cus()
     return cus;
 }
 
-int persistent_grid(int64_t ntiles, int blocks_per_cu)
+int resident_blocks(const void* kernel, int threads)
 {
-    int64_t g = (int64_t)num_cus() * blocks_per_cu;
+    static std::mutex mu;
+    static std::unordered_map<const void*, int> cache;
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = cache.find(kernel);
+    if (it != cache.end()) return it->second;
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, threads, 0) != hipSuccess || nb < 1)
+        nb = 1;
+    cache.emplace(kernel, nb);
+    return nb;
+}
+
+int persistent_grid(int64_t ntiles, int blocks_per_cu, int resident)
+{
+    int64_t g = (int64_t)num_cus() * std::min(blocks_per_cu, resident);
     g = std::min<int64_t>(g, kMaxGrid);
     g = std::min<int64_t>(g, std::max<int64_t>(ntiles, 1));
     if (g >= kNumXcd) g -= g % kNumXcd;
@@ -498,10 +511,18 @@ Sell<float> sell_view<float>(const sspcg_matrix* A)
     return {A->n, A->nslices, A->slice_ptr, A->slice_aux, A->scol, A->soff, A->sval32, A->dinv32};
 }
 
-static int spmv_grid(const sspcg_matrix* A)
+static int64_t spmv_tiles(const sspcg_matrix* A)
 {
-    const int64_t ntiles = (A->nslices + kRowBlock / kSlice - 1) / (kRowBlock / kSlice);
-    return persistent_grid(ntiles, 8);
+    return (A->nslices + kRowBlock / kSlice - 1) / (kRowBlock / kSlice);
+}
+
+// Persistent grid for the SpMV kernels that also reduce: all workgroups
+// resident at once.
+template <typename K>
+static int spmv_reduce_grid(const sspcg_matrix* A, K kernel)
+{
+    const int resident = resident_blocks(reinterpret_cast<const void*>(kernel), kRowBlock);
+    return persistent_grid(spmv_tiles(A), 8, resident);
 }
 
 int matrix_inspect(sspcg_matrix* A, const double* val, bool values_only, LayoutPlan* plan,
@@ -609,7 +630,7 @@ int launch_spmv(const sspcg_matrix* A, int mode, const T* x, T* y, const T* zpre
                 double c1, double c2, double c3, const Ctrl* ctrl, hipStream_t st)
 {
     const Sell<T> S = sell_view<T>(A);
-    const int G = spmv_grid(A);
+    const int64_t G = spmv_tiles(A);
     if (mode == 0)
         hipLaunchKernelGGL((k_spmv<T, 0>), dim3(G), dim3(kRowBlock), 0, st, S, x, y, zprev, znext,
                            c1, c2, c3, ctrl);
@@ -634,7 +655,7 @@ int launch_residual(const sspcg_matrix* A, const double* x, const double* b, TR*
 {
     const Sell<double> S = sell_view<double>(A);
     const TR* dinvT = sell_view<TR>(A).dinv;
-    const int G = spmv_grid(A);
+    const int G = spmv_reduce_grid(A, k_residual<TR>);
     hipLaunchKernelGGL((k_residual<TR>), dim3(G), dim3(kRowBlock), 0, st, S, x, b, r, z1, dinvT,
                        partials);
     SSPCG_LAUNCHED("k_residual");
@@ -650,7 +671,7 @@ template int launch_residual<float>(const sspcg_matrix*, const double*, const do
 int launch_pcg_spmv(const sspcg_matrix* A, const double* p, double* q, double* partials,
                     int* G_out, const Ctrl* ctrl, hipStream_t st)
 {
-    const int G = spmv_grid(A);
+    const int G = spmv_reduce_grid(A, k_pcg_spmv);
     hipLaunchKernelGGL(k_pcg_spmv, dim3(G), dim3(kRowBlock), 0, st, sell_view<double>(A), p, q,
                        partials, ctrl);
     SSPCG_LAUNCHED("k_pcg_spmv");

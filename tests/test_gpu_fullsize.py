@@ -47,7 +47,8 @@ def test_layout_of_full_workload(big):
     info = M.info()
     assert A.nnz == (3 * N - 2) ** 3
     assert info["slices"] == info["shared_slices"] == A.n // 64
-    assert info["slots"] == 27 * A.n
+    assert A.nnz <= info["slots"] <= 27 * A.n
+    assert info["slots"] <= 1.01 * A.nnz
 
 
 def test_spmv_sampled_rows(big):

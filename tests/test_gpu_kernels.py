@@ -367,7 +367,9 @@ def test_stencil_slices_use_shared_offsets():
     A = si.stencil("27pt", N, si.coeff_blocks(N))
     M = P.Matrix.from_csr(A, device=DEV)
     info = M.info()
-    assert info["slots"] == 27 * N**3      # every row padded to the 27 offsets
+    # every slice shares one offset list: the 27 stencil offsets inside the
+    # grid, fewer on boundary planes (slices hold 64 rows of one x-line half)
     assert info["shared_slices"] == info["slices"] == N**3 // 64
+    assert A.nnz <= info["slots"] <= 27 * N**3
     # values only: 8 bytes per slot plus small metadata, no column indices
     assert info["device_bytes"] < 8 * info["slots"] + 40 * A.n
