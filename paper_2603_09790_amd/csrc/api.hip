@@ -742,16 +742,18 @@ int sspcg_matrix_create(int32_t n, int32_t nnz, const int32_t* row_ptr, const in
     if (A->slots >= ((int64_t)1 << 40)) return fail_union(arg_error("matrix too large"));
     const size_t b_col = align_up(sizeof(int32_t) * (size_t)plan.ncol, 256);
     const size_t b_off = align_up(sizeof(int32_t) * (size_t)plan.nsoff, 256);
+    const size_t b_mask = plan.nshared ? align_up(sizeof(uint32_t) * (size_t)A->nslices * kSlice, 256) : 0;
     const size_t b_val = align_up(sizeof(double) * (size_t)A->slots, 256);
     const size_t b_val32 = f32 ? align_up(sizeof(float) * (size_t)A->slots, 256) : 0;
-    e = hipMalloc(&A->mem_vals, b_col + b_off + b_val + b_val32);
+    e = hipMalloc(&A->mem_vals, b_col + b_off + b_mask + b_val + b_val32);
     if (e != hipSuccess) return fail_union(hip_fail(e, "hipMalloc(matrix values)"));
     char* mv = static_cast<char*>(A->mem_vals);
     A->scol = reinterpret_cast<int32_t*>(mv);
     A->soff = reinterpret_cast<int32_t*>(mv + b_col);
-    A->sval = reinterpret_cast<double*>(mv + b_col + b_off);
-    A->sval32 = f32 ? reinterpret_cast<float*>(mv + b_col + b_off + b_val) : nullptr;
-    A->mem_bytes = b_small + b_col + b_off + b_val + b_val32;
+    A->smask = plan.nshared ? reinterpret_cast<uint32_t*>(mv + b_col + b_off) : nullptr;
+    A->sval = reinterpret_cast<double*>(mv + b_col + b_off + b_mask);
+    A->sval32 = f32 ? reinterpret_cast<float*>(mv + b_col + b_off + b_mask + b_val) : nullptr;
+    A->mem_bytes = b_small + b_col + b_off + b_mask + b_val + b_val32;
     e = hipMemcpyAsync(A->slice_ptr, plan.slice_ptr.data(), sizeof(int64_t) * plan.slice_ptr.size(),
                        hipMemcpyHostToDevice, st);
     if (e == hipSuccess)

@@ -40,10 +40,11 @@ static_assert(sizeof(Ctrl) == 128, "Ctrl layout");
 // lane; entry k of lane l sits at slot slice_ptr[c] + 64k + l.  Two kinds of
 // slice:
 //  - shared offsets (slice_aux[c] < 0): the slice's rows draw their columns
-//    from one sorted list of offsets o_k = col - row, stored once at
-//    soff[-slice_aux[c] - 1 + k]; entry k of a row is its value at column
-//    row + o_k, or 0 where the row has no such entry.  This is the case for
-//    stencil matrices and removes the column indices from the stream.
+//    from one sorted list of at most 32 offsets o_k = col - row, stored once
+//    at soff[-slice_aux[c] - 1 + k]; entry k of a row is its value at column
+//    row + o_k, or 0 where the row has no such entry, and bit k of the row's
+//    mask smask[row] says whether it has one.  This is the case for stencil
+//    matrices and removes the column indices from the stream.
 //  - explicit columns (slice_aux[c] >= 0): entry k holds the row's k-th
 //    stored entry, its column at col[slice_aux[c] + 64k + l]; rows are padded
 //    to the slice's longest row with value 0 and the row as column.
@@ -56,12 +57,13 @@ struct Sell {
     const int64_t* slice_aux;   // kind and offset of each slice, see above
     const int32_t* col;         // explicit column indices
     const int32_t* soff;        // shared offset lists
+    const uint32_t* smask;      // per row (nslices * 64): entries present at the offsets
     const T* val;
     const T* dinv;              // 1 / diag(A)
 };
 
-// Longest shared offset list a slice may use.
-constexpr int kMaxUnion = 64;
+// Longest shared offset list a slice may use (the width of a row mask).
+constexpr int kMaxUnion = 32;
 
 // Grid of a persistent row kernel: at most `blocks_per_cu` workgroups per CU
 // and never more than fit at once (`resident`, from the occupancy of the

@@ -14,13 +14,14 @@ struct sspcg_matrix {
     int64_t* slice_aux = nullptr;       // owned (inside `mem`)
     int32_t* scol = nullptr;            // owned (inside `mem_vals`)
     int32_t* soff = nullptr;            // owned (inside `mem_vals`)
+    uint32_t* smask = nullptr;          // owned (inside `mem_vals`)
     double* sval = nullptr;
     float* sval32 = nullptr;
     double* dinv = nullptr;
     float* dinv32 = nullptr;
     int32_t* dflags = nullptr;
     void* mem = nullptr;                // device allocation: slice_ptr/aux, dinv, dinv32, dflags
-    void* mem_vals = nullptr;           // device allocation: scol, soff, sval, sval32
+    void* mem_vals = nullptr;           // device allocation: scol, soff, smask, sval, sval32
     size_t mem_bytes = 0;
     sspcg::Ctrl* host_ctrl = nullptr;   // pinned mirror for polling (2 entries)
     sspcg_profile profile{};            // last profiled solve

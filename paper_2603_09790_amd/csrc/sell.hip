@@ -148,6 +148,7 @@ __global__ __launch_bounds__(kRowBlock) void k_fill(int32_t n, int64_t nslices,
                                                     const int64_t* __restrict__ slice_aux,
                                                     const int32_t* __restrict__ soff,
                                                     int32_t* __restrict__ scol,
+                                                    uint32_t* __restrict__ smask,
                                                     double* __restrict__ sval,
                                                     float* __restrict__ sval32, bool values_only)
 {
@@ -165,16 +166,19 @@ __global__ __launch_bounds__(kRowBlock) void k_fill(int32_t n, int64_t nslices,
     if (aux < 0) {
         const int32_t* off = soff + (-aux - 1);
         int32_t p = 0;
+        uint32_t mask = 0;
         for (int k = 0; k < w; ++k) {
             double v = 0.0;
             if (p < len && col[a + p] - (int32_t)i == off[k]) {
                 v = val[a + p];
+                mask |= 1u << k;
                 ++p;
             }
             const int64_t slot = base + (int64_t)k * kSlice + lane;
             sval[slot] = v;
             if (sval32) sval32[slot] = (float)v;
         }
+        if (!values_only) smask[i] = mask;
     } else {
         for (int k = 0; k < w; ++k) {
             const int64_t slot = base + (int64_t)k * kSlice + lane;
@@ -228,10 +232,13 @@ __device__ inline double row_explicit(const int32_t* __restrict__ cp, const T* _
 }
 
 // Sum of one row of a shared-offset slice: entry k multiplies x[row + o_k],
-// or x[self] (an exact zero term) where the row has no entry at o_k.
+// or x[self] (with the stored zero: an exact zero term) where bit k of the
+// row's mask is clear.  The gather addresses depend only on the mask and the
+// offsets, so values and gathers are in flight together.
 template <typename T, int U>
 __device__ inline double row_shared(const int32_t* __restrict__ off, const T* __restrict__ vp, int w,
-                                    int32_t row, int32_t self, const T* __restrict__ x)
+                                    uint32_t mask, int32_t row, int32_t self,
+                                    const T* __restrict__ x)
 {
     double acc = 0.0;
     int k = 0;
@@ -240,13 +247,13 @@ __device__ inline double row_shared(const int32_t* __restrict__ off, const T* __
 #pragma unroll
         for (int u = 0; u < U; ++u) vv[u] = ld_stream(vp + (int64_t)(k + u) * kSlice);
 #pragma unroll
-        for (int u = 0; u < U; ++u) xx[u] = x[vv[u] != T(0) ? row + off[k + u] : self];
+        for (int u = 0; u < U; ++u) xx[u] = x[(mask >> (k + u)) & 1u ? row + off[k + u] : self];
 #pragma unroll
         for (int u = 0; u < U; ++u) acc = fma((double)vv[u], (double)xx[u], acc);
     }
     for (; k < w; ++k) {
         const T vv = ld_stream(vp + (int64_t)k * kSlice);
-        acc = fma((double)vv, (double)x[vv != T(0) ? row + off[k] : self], acc);
+        acc = fma((double)vv, (double)x[(mask >> k) & 1u ? row + off[k] : self], acc);
     }
     return acc;
 }
@@ -262,8 +269,8 @@ __device__ inline double slice_row(const Sell<T>& A, int64_t c, int lane, const 
     const int64_t row = c * kSlice + lane;
     if (aux < 0) {
         const int32_t self = (int32_t)(row < A.n ? row : A.n - 1);
-        return row_shared<T, kUnroll>(A.soff + (-aux - 1), A.val + base + lane, w, (int32_t)row,
-                                      self, x);
+        return row_shared<T, kUnroll>(A.soff + (-aux - 1), A.val + base + lane, w, A.smask[row],
+                                      (int32_t)row, self, x);
     }
     return row_explicit<T, kUnroll>(A.col + aux + lane, A.val + base + lane, w, x);
 }
@@ -502,13 +509,15 @@ Sell<T> sell_view(const sspcg_matrix* A);
 template <>
 Sell<double> sell_view<double>(const sspcg_matrix* A)
 {
-    return {A->n, A->nslices, A->slice_ptr, A->slice_aux, A->scol, A->soff, A->sval, A->dinv};
+    return {A->n, A->nslices, A->slice_ptr, A->slice_aux, A->scol, A->soff, A->smask, A->sval,
+            A->dinv};
 }
 
 template <>
 Sell<float> sell_view<float>(const sspcg_matrix* A)
 {
-    return {A->n, A->nslices, A->slice_ptr, A->slice_aux, A->scol, A->soff, A->sval32, A->dinv32};
+    return {A->n, A->nslices, A->slice_ptr, A->slice_aux, A->scol, A->soff, A->smask, A->sval32,
+            A->dinv32};
 }
 
 static int64_t spmv_tiles(const sspcg_matrix* A)
@@ -604,8 +613,8 @@ int matrix_fill(sspcg_matrix* A, const double* val, bool values_only, hipStream_
     const int64_t nrows_padded = A->nslices * kSlice;
     const int blocks = (int)((nrows_padded + kRowBlock - 1) / kRowBlock);
     hipLaunchKernelGGL(k_fill, dim3(blocks), dim3(kRowBlock), 0, st, A->n, A->nslices, A->row_ptr,
-                       A->col, val, A->slice_ptr, A->slice_aux, A->soff, A->scol, A->sval,
-                       A->sval32, values_only);
+                       A->col, val, A->slice_ptr, A->slice_aux, A->soff, A->scol, A->smask,
+                       A->sval, A->sval32, values_only);
     SSPCG_LAUNCHED("k_fill");
     SSPCG_HIP(hipStreamSynchronize(st));
     return SSPCG_OK;
