@@ -204,8 +204,9 @@ def main() -> int:
         mpk_calls = sp["launches"] / s
         b_mpk = spmv_family_bytes(n, nnz, s, 8, col_frac)
         achieved = b_mpk * mpk_calls / (sp["ms"] / 1e3) / 1e9
+        traffic = counter_traffic() if (args.N == 192 and s == 6) else None
         out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                           "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                           "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                            "kernel": "k_spmv (matrix powers kernel, FP64)",
                            "avg_launch_us": 1e3 * sp["ms"] / sp["launches"],
                            "bytes_per_launch": b_mpk / s,
@@ -247,6 +248,24 @@ def main() -> int:
 L_PHASES = ["spmv", "gram_update", "gram_rect", "fgs", "norm", "xr"]
 
 COPY_BYTES = 1 << 30   # calibration copy: 1 GiB read + 1 GiB written
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "traffic_k_spmv_27pt_192.json")
+
+
+def counter_traffic():
+    """HBM bytes per SpMV launch measured by rocprofv3 counters (FETCH_SIZE,
+    WRITE_SIZE, scaled by a copy of known size), from the committed record --
+    or None when the SpMV sources changed since the counters were taken."""
+    import hashlib
+    try:
+        rec = json.load(open(TRAFFIC_RECORD))
+        h = hashlib.sha256()
+        for f in rec["sources"]:
+            h.update(open(os.path.join(ROOT, f), "rb").read())
+        if h.hexdigest() != rec["source_sha256"]:
+            return None
+        return rec["traffic_bytes_per_launch"]
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def kernel_pass(P, torch, M, A, b, interval, args, col_frac):
