@@ -111,9 +111,13 @@ def main() -> int:
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-profile", action="store_true",
                     help="time without the per-phase HIP events")
-    ap.add_argument("--mode", choices=["solve", "kernels"], default="solve",
+    ap.add_argument("--mode", choices=["solve", "kernels", "paper"], default="solve",
                     help="kernels: a few launches of each hot kernel on the workload and a "
-                         "copy kernel of known size (for rocprofv3 counter passes)")
+                         "copy kernel of known size (for rocprofv3 counter passes); paper: the "
+                         "paper's Gram-solve experiments on its own workload shape")
+    ap.add_argument("--paper-N", type=int, default=200)
+    ap.add_argument("--paper-out", default=None,
+                    help="paper mode: also write the per-iteration histories to this JSON file")
     ap.add_argument("--reps", type=int, default=5)
     args = ap.parse_args()
 
@@ -132,6 +136,13 @@ def main() -> int:
         return 1
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+
+    if args.mode == "paper":
+        out = paper_experiments(P, torch, dev, args)
+        print(json.dumps(out["summary"]), flush=True)
+        if args.paper_out:
+            json.dump(out, open(args.paper_out, "w"))
+        return 0
 
     A, b_np, interval = build_workload(args.N)
     t0 = time.time()
@@ -266,6 +277,54 @@ def counter_traffic():
         return rec["traffic_bytes_per_launch"]
     except (OSError, KeyError, ValueError):
         return None
+
+
+def paper_experiments(P, torch, dev, args):
+    """The paper's Gram-solve experiments (Sec. 3.4 and its residual-history
+    comparison) on one GPU's share of its weak-scaling workload: the
+    constant-coefficient 27-point matrix as in HPCG on N^3 (N = 200 per GPU
+    in the paper), unit right-hand side, lambda_min = 0 and a power-method
+    lambda_max (Sec. 2), tolerance 1e-8.
+
+    For s in {4, 6}: FGS with 30 and 60 sweeps and the Cholesky Gram solve,
+    recording per outer iteration the relative residual and the reduced-system
+    residuals eta_alpha, eta_beta; classical PCG with its residual sampled
+    every s steps for the aligned comparison.
+    """
+    import sspcg_inputs as si
+    N = args.paper_N
+    t0 = time.time()
+    A = si.hpcg27(N)
+    b_np = np.ones(A.n)
+    interval = si.power_bounds(A)
+    log(f"[paper] 27pt HPCG {N}^3: n={A.n} nnz={A.nnz}, power-method interval {interval} "
+        f"({time.time() - t0:.1f}s)")
+    M = P.Matrix.from_csr(A, device=dev)
+    b = torch.from_numpy(b_np).to(dev)
+    tol = 1e-8
+    _, ip = P.pcg(M, b, tol=tol, history=True)
+    hp = ip["history"]
+    runs, summary = {}, {"workload": f"27-point Poisson (HPCG) {N}^3, b = 1, power-method interval",
+                         "n": A.n, "nnz": A.nnz, "interval": list(interval), "tol": tol,
+                         "pcg": {"iters": ip["outer_iters"], "time_s": ip["device_ms"] / 1e3}}
+    for s in (4, 6):
+        for gram, sweeps in (("fgs", 30), ("fgs", 60), ("cholesky", 1)):
+            x, info = P.solve(M, b, s=s, sweeps=sweeps, gram=gram, interval=interval, tol=tol,
+                              history=True)
+            h = info["history"]
+            k = np.arange(1, len(h) + 1)
+            aligned = hp[np.minimum(k * s, len(hp)) - 1]
+            name = f"s{s}_{gram}{sweeps if gram == 'fgs' else ''}"
+            runs[name] = {"relres": h[:, 0].tolist(), "eta_alpha": h[:, 1].tolist(),
+                          "eta_beta": h[:, 2].tolist(), "pcg_every_s": aligned.tolist()}
+            eb = h[:-1, 2] if len(h) > 1 else h[:, 2]
+            summary[name] = {"outer_iters": info["outer_iters"], "krylov_steps": s * info["outer_iters"],
+                             "time_s": info["device_ms"] / 1e3, "status": info["status_name"],
+                             "eta_alpha_max": float(h[:, 1].max()), "eta_alpha_median": float(np.median(h[:, 1])),
+                             "eta_beta_max": float(eb.max()), "eta_beta_median": float(np.median(eb)),
+                             "max_log10_gap_to_pcg": float(np.max(np.abs(np.log10(h[:, 0]) - np.log10(aligned))))}
+            log(f"[paper] {name}: {summary[name]}")
+    return {"summary": summary, "runs": runs, "pcg_history": hp.tolist()}
 
 
 def kernel_pass(P, torch, M, A, b, interval, args, col_frac):

@@ -740,6 +740,35 @@ int sspcg_matrix_create(int32_t n, int32_t nnz, const int32_t* row_ptr, const in
     A->slots = plan.slots;
     A->nshared = plan.nshared;
     if (A->slots >= ((int64_t)1 << 40)) return fail_union(arg_error("matrix too large"));
+    if (!plan.uoff.empty()) {
+        // uniform layout: offsets, masks and vector-grouped values only
+        A->uniform = 1;
+        A->uw = (int32_t)plan.uoff.size();
+        A->slots = A->nslices * kSlice * A->uw;
+        const int64_t rows = A->nslices * kSlice;
+        const size_t b_uoff = 256;
+        const size_t b_mask = align_up(sizeof(uint32_t) * (size_t)rows, 256);
+        const size_t b_val = align_up(sizeof(double) * (size_t)rows * ((A->uw + 1) / 2 * 2), 256);
+        const size_t b_val32 = f32 ? align_up(sizeof(float) * (size_t)rows * ((A->uw + 3) / 4 * 4), 256) : 0;
+        e = hipMalloc(&A->mem_vals, b_uoff + b_mask + b_val + b_val32);
+        if (e != hipSuccess) return fail_union(hip_fail(e, "hipMalloc(matrix values)"));
+        char* mv = static_cast<char*>(A->mem_vals);
+        A->uoff = reinterpret_cast<int32_t*>(mv);
+        A->smask = reinterpret_cast<uint32_t*>(mv + b_uoff);
+        A->sval = reinterpret_cast<double*>(mv + b_uoff + b_mask);
+        A->sval32 = f32 ? reinterpret_cast<float*>(mv + b_uoff + b_mask + b_val) : nullptr;
+        A->mem_bytes = b_small + b_uoff + b_mask + b_val + b_val32;
+        e = hipMemcpyAsync(A->uoff, plan.uoff.data(), sizeof(int32_t) * plan.uoff.size(),
+                           hipMemcpyHostToDevice, st);
+        if (e != hipSuccess) return fail_union(hip_fail(e, "offsets"));
+        e = hipFreeAsync(d_union, st);
+        d_union = nullptr;
+        if (e != hipSuccess) return fail(hip_fail(e, "hipFreeAsync"));
+        rc = matrix_fill(A, val, false, st);
+        if (rc != SSPCG_OK) return fail(rc);
+        *out = A;
+        return SSPCG_OK;
+    }
     const size_t b_col = align_up(sizeof(int32_t) * (size_t)plan.ncol, 256);
     const size_t b_off = align_up(sizeof(int32_t) * (size_t)plan.nsoff, 256);
     const size_t b_mask = plan.nshared ? align_up(sizeof(uint32_t) * (size_t)A->nslices * kSlice, 256) : 0;

@@ -49,9 +49,19 @@ static_assert(sizeof(Ctrl) == 128, "Ctrl layout");
 //    stored entry, its column at col[slice_aux[c] + 64k + l]; rows are padded
 //    to the slice's longest row with value 0 and the row as column.
 // Either way the entries of a row keep the CSR order.
+//
+// Uniform layout (uniform != 0): when the offsets of all slices fit one
+// global sorted list of at most 32 (structured-grid stencils), every row is
+// stored against that list, no per-slice data is needed and a lane's
+// entries are grouped in 16-byte vectors (2 FP64 or 4 FP32 values): entry k
+// of lane l of slice c sits at c*64*uwv + (k/V)*64*V + l*V + k%V, V = 16 /
+// sizeof(T), uwv = the list length rounded up to a multiple of V.
 template <typename T>
 struct Sell {
     int32_t n;
+    int32_t uniform;
+    int32_t uw, uwv;            // uniform: offsets in the list, stored entries per row
+    const int32_t* uoff;        // uniform: the global offset list
     int64_t nslices;
     const int64_t* slice_ptr;   // nslices + 1 slot offsets, multiples of 64
     const int64_t* slice_aux;   // kind and offset of each slice, see above

@@ -15,6 +15,8 @@ struct sspcg_matrix {
     int32_t* scol = nullptr;            // owned (inside `mem_vals`)
     int32_t* soff = nullptr;            // owned (inside `mem_vals`)
     uint32_t* smask = nullptr;          // owned (inside `mem_vals`)
+    int32_t uniform = 0, uw = 0;        // uniform layout: global offset list length
+    int32_t* uoff = nullptr;            // owned (inside `mem_vals`)
     double* sval = nullptr;
     float* sval32 = nullptr;
     double* dinv = nullptr;
@@ -40,6 +42,7 @@ Sell<T> sell_view(const sspcg_matrix* A);
 struct LayoutPlan {
     std::vector<int64_t> slice_ptr, slice_aux;
     int64_t slots = 0, ncol = 0, nsoff = 0, nshared = 0;
+    std::vector<int32_t> uoff;          // non-empty: use the uniform layout with these offsets
 };
 int matrix_inspect(sspcg_matrix* A, const double* val, bool values_only, LayoutPlan* plan,
                    int32_t** d_union, hipStream_t st);

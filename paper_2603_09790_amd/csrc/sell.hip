@@ -195,6 +195,50 @@ __global__ __launch_bounds__(kRowBlock) void k_fill(int32_t n, int64_t nslices,
     }
 }
 
+// Uniform layout: one thread per row walks its sorted columns against the
+// global offset list; slot of entry k in FP64 (pairs) and FP32 (quads).
+__device__ inline int64_t uslot(int64_t c, int k, int lane, int uwv, int V)
+{
+    return c * kSlice * uwv + (int64_t)(k / V) * (kSlice * V) + lane * V + k % V;
+}
+
+__global__ __launch_bounds__(kRowBlock) void k_fill_uniform(int32_t n, int64_t nslices,
+                                                            const int32_t* __restrict__ rp,
+                                                            const int32_t* __restrict__ col,
+                                                            const double* __restrict__ val,
+                                                            const int32_t* __restrict__ uoff, int uw,
+                                                            int uwv64, int uwv32,
+                                                            uint32_t* __restrict__ smask,
+                                                            double* __restrict__ sval,
+                                                            float* __restrict__ sval32,
+                                                            bool values_only)
+{
+    const int64_t i = (int64_t)blockIdx.x * kRowBlock + threadIdx.x;
+    const int64_t c = i / kSlice;
+    if (c >= nslices) return;
+    const int lane = (int)(i % kSlice);
+    int32_t a = 0, len = 0;
+    if (i < n) {
+        a = rp[i];
+        len = rp[i + 1] - a;
+    }
+    double v[kMaxUnion];
+    uint32_t mask = 0;
+    int32_t p = 0;
+    for (int k = 0; k < uw; ++k) {
+        v[k] = 0.0;
+        if (p < len && col[a + p] - (int32_t)i == uoff[k]) {
+            v[k] = val[a + p];
+            mask |= 1u << k;
+            ++p;
+        }
+    }
+    for (int k = 0; k < uwv64; ++k) sval[uslot(c, k, lane, uwv64, 2)] = k < uw ? v[k] : 0.0;
+    if (sval32)
+        for (int k = 0; k < uwv32; ++k) sval32[uslot(c, k, lane, uwv32, 4)] = k < uw ? (float)v[k] : 0.0f;
+    if (!values_only) smask[i] = mask;
+}
+
 // ------------------------------------------------------------------ SpMV
 
 template <typename T>
@@ -260,10 +304,64 @@ __device__ inline double row_shared(const int32_t* __restrict__ off, const T* __
 
 constexpr int kUnroll = 9;
 
+template <typename T>
+struct Vec16;
+template <>
+struct Vec16<double> {
+    typedef double type __attribute__((ext_vector_type(2)));
+};
+template <>
+struct Vec16<float> {
+    typedef float type __attribute__((ext_vector_type(4)));
+};
+
+// Row of the uniform layout: NV 16-byte vectors per lane (NV > 0: known at
+// compile time, fully unrolled; NV = 0: runtime count).  The gather index
+// depends only on the mask and the offsets, so all loads are independent.
+template <typename T, int NV>
+__device__ inline double row_uniform(const Sell<T>& A, int64_t c, int lane,
+                                     const T* __restrict__ x)
+{
+    constexpr int V = 16 / sizeof(T);
+    typedef typename Vec16<T>::type VT;
+    const int64_t row = c * kSlice + lane;
+    const int32_t self = (int32_t)(row < A.n ? row : A.n - 1);
+    const uint32_t m = A.smask[row];
+    const VT* vp = reinterpret_cast<const VT*>(A.val + c * kSlice * A.uwv) + lane;
+    const int nv = NV > 0 ? NV : A.uwv / V;
+    double acc = 0.0;
+#pragma unroll 4
+    for (int j = 0; j < nv; ++j) {
+        const VT v = __builtin_nontemporal_load(vp + (int64_t)j * kSlice);
+#pragma unroll
+        for (int h = 0; h < V; ++h) {
+            const int k = j * V + h;
+            const int32_t idx = (m >> k) & 1u ? (int32_t)row + A.uoff[k] : self;
+            acc = fma((double)v[h], (double)x[idx], acc);
+        }
+    }
+    return acc;
+}
+
+template <typename T>
+__device__ inline double uniform_row(const Sell<T>& A, int64_t c, int lane, const T* __restrict__ x)
+{
+    constexpr int V = 16 / sizeof(T);
+    switch (A.uwv / V) {
+    case 2: return row_uniform<T, 2>(A, c, lane, x);     // 5-point (FP32)
+    case 3: return row_uniform<T, 3>(A, c, lane, x);     // 5-point (FP64)
+    case 4: return row_uniform<T, 4>(A, c, lane, x);     // 7-point (FP64)
+    case 7: return row_uniform<T, 7>(A, c, lane, x);     // 27-point (FP32)
+    case 14: return row_uniform<T, 14>(A, c, lane, x);   // 27-point (FP64)
+    default: return row_uniform<T, 0>(A, c, lane, x);
+    }
+}
+
 // (A x)_row for the row of this lane in slice c (c < nslices).
 template <typename T>
 __device__ inline double slice_row(const Sell<T>& A, int64_t c, int lane, const T* __restrict__ x)
 {
+    if (A.uniform) return uniform_row<T>(A, c, lane, x);
     const int64_t base = A.slice_ptr[c], aux = A.slice_aux[c];
     const int w = (int)((A.slice_ptr[c + 1] - base) / kSlice);
     const int64_t row = c * kSlice + lane;
@@ -509,15 +607,15 @@ Sell<T> sell_view(const sspcg_matrix* A);
 template <>
 Sell<double> sell_view<double>(const sspcg_matrix* A)
 {
-    return {A->n, A->nslices, A->slice_ptr, A->slice_aux, A->scol, A->soff, A->smask, A->sval,
-            A->dinv};
+    return {A->n, A->uniform, A->uw, (A->uw + 1) / 2 * 2, A->uoff, A->nslices, A->slice_ptr,
+            A->slice_aux, A->scol, A->soff, A->smask, A->sval, A->dinv};
 }
 
 template <>
 Sell<float> sell_view<float>(const sspcg_matrix* A)
 {
-    return {A->n, A->nslices, A->slice_ptr, A->slice_aux, A->scol, A->soff, A->smask, A->sval32,
-            A->dinv32};
+    return {A->n, A->uniform, A->uw, (A->uw + 3) / 4 * 4, A->uoff, A->nslices, A->slice_ptr,
+            A->slice_aux, A->scol, A->soff, A->smask, A->sval32, A->dinv32};
 }
 
 static int64_t spmv_tiles(const sspcg_matrix* A)
@@ -596,6 +694,34 @@ int matrix_inspect(sspcg_matrix* A, const double* val, bool values_only, LayoutP
         plan->slice_ptr[c + 1] = plan->slice_ptr[c] + w * kSlice;
     }
     plan->slots = plan->slice_ptr[A->nslices];
+    // uniform layout: every slice shared, and the union of all their lists
+    // fits one mask and costs at most 2 % more stored entries
+    plan->uoff.clear();
+    if (plan->nshared == A->nslices) {
+        std::vector<int32_t> hun((size_t)A->nslices * kMaxUnion);
+        SSPCG_HIP(hipMemcpy(hun.data(), *d_union, sizeof(int32_t) * hun.size(),
+                            hipMemcpyDeviceToHost));
+        std::vector<int32_t> all;
+        all.reserve(64);
+        bool fits = true;
+        for (int64_t c = 0; c < A->nslices && fits; ++c) {
+            for (int k = 0; k < ulen[c]; ++k) {
+                const int32_t o = hun[(size_t)c * kMaxUnion + k];
+                if (std::find(all.begin(), all.end(), o) == all.end()) {
+                    all.push_back(o);
+                    if ((int)all.size() > kMaxUnion) {
+                        fits = false;
+                        break;
+                    }
+                }
+            }
+        }
+        if (fits && !all.empty() &&
+            (double)A->nslices * kSlice * all.size() <= 1.02 * (double)plan->slots) {
+            std::sort(all.begin(), all.end());
+            plan->uoff = all;
+        }
+    }
     return SSPCG_OK;
 }
 
@@ -612,6 +738,14 @@ int matrix_fill(sspcg_matrix* A, const double* val, bool values_only, hipStream_
 {
     const int64_t nrows_padded = A->nslices * kSlice;
     const int blocks = (int)((nrows_padded + kRowBlock - 1) / kRowBlock);
+    if (A->uniform) {
+        hipLaunchKernelGGL(k_fill_uniform, dim3(blocks), dim3(kRowBlock), 0, st, A->n, A->nslices,
+                           A->row_ptr, A->col, val, A->uoff, A->uw, (A->uw + 1) / 2 * 2,
+                           (A->uw + 3) / 4 * 4, A->smask, A->sval, A->sval32, values_only);
+        SSPCG_LAUNCHED("k_fill_uniform");
+        SSPCG_HIP(hipStreamSynchronize(st));
+        return SSPCG_OK;
+    }
     hipLaunchKernelGGL(k_fill, dim3(blocks), dim3(kRowBlock), 0, st, A->n, A->nslices, A->row_ptr,
                        A->col, val, A->slice_ptr, A->slice_aux, A->soff, A->scol, A->smask,
                        A->sval, A->sval32, values_only);

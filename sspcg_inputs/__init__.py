@@ -320,14 +320,19 @@ def power_bounds(A: CSR, rtol: float = 1e-3, max_iter: int = 50,
     after max_iter steps (Sec. "The s-step PCG method with Chebyshev Krylov
     basis").
     """
-    S = to_scipy(A)
+    from . import _native
+    L = _native.lib()
     dinv = jacobi_inverse(A)
+    ones = np.ones(A.n)
+    Av = np.empty(A.n)
     v = np.random.default_rng(seed).uniform(-1.0, 1.0, size=A.n)
     v /= np.linalg.norm(v)
     lam_old = 0.0
     lam = 0.0
     for _ in range(max_iter):
-        w = dinv * (S @ v)
+        L.inp_scaled_matvec(A.n, A.row_ptr.ctypes.data, A.col.ctypes.data, A.val.ctypes.data,
+                            ones.ctypes.data, v.ctypes.data, Av.ctypes.data)
+        w = dinv * Av
         lam = float(np.linalg.norm(w))
         v = w / lam
         if abs(lam - lam_old) < rtol * abs(lam):
