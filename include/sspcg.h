@@ -89,6 +89,9 @@ typedef struct {
     int32_t gram;               /* sspcg_gram_solver */
     int32_t check_every;        /* outer iterations enqueued between host polls (>= 1) */
     int32_t profile;            /* 1: time every phase with HIP events (sspcg_last_profile) */
+    double sweep_tol;           /* 0: exactly `sweeps` FGS sweeps.  > 0: each right-hand side
+                                   stops sweeping once ||m - W a|| <= sweep_tol ||m|| (the
+                                   accuracy criterion of Sec. 3), after at most `sweeps` */
 } sspcg_params;
 
 /* Outcome of a solve (host struct filled by the solve calls). */
@@ -227,11 +230,13 @@ int sspcg_gram_rect(int64_t n, int32_t s, int32_t dtype, const void* Q, const vo
 
 /* FGS (or Cholesky) solve of W X = B for nrhs right-hand sides: B, X device
  * double s x nrhs row-major, W device double s x s (lower triangle read).
- * `sweeps` sweeps of (D + L_W) x_new = b - L_W^T x_old from x = 0.
+ * `sweeps` sweeps of (D + L_W) x_new = b - L_W^T x_old from x = 0; with
+ * sweep_tol > 0 a column stops early once ||b - W x|| <= sweep_tol ||b||.
  * status (device int32): set to SSPCG_ERR_BREAKDOWN for W_ii <= 0 and to
  * SSPCG_ERR_NONFINITE for NaN/Inf in W or B, else SSPCG_OK. */
 int sspcg_fgs(int32_t s, int32_t nrhs, const double* W, const double* B, int32_t sweeps,
-              int32_t gram_solver, double* X, int32_t* status, sspcg_stream stream);
+              double sweep_tol, int32_t gram_solver, double* X, int32_t* status,
+              sspcg_stream stream);
 
 /* x += Q alpha; r -= AQ alpha; rr = ||r||^2 (device double, FP64 sum);
  * when z1 != NULL also z1 = M^{-1} r.  alpha: device double s. */

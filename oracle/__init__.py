@@ -73,13 +73,14 @@ def lib():
         "or_gram_rect": (None, [_I64, _I, _P, _P, _I64, _P]),
         "or_gram_rect_f32": (None, [_I64, _I, _P, _P, _I64, _P]),
         "or_fgs": (_I, [_I, _I, _P, _P, _I, _P]),
+        "or_fgs_tol": (_I, [_I, _I, _P, _P, _I, _D, _P]),
         "or_chol_solve": (_I, [_I, _I, _P, _P, _P]),
         "or_xr_update": (None, [_I64, _I, _P, _P, _P, _I64, _P, _P]),
         "or_xr_update_f32": (None, [_I64, _I, _P, _P, _P, _I64, _P, _P]),
         "or_block_update": (None, [_I64, _I, _P, _P, _P, _P, _P, _I64]),
         "or_block_update_f32": (None, [_I64, _I, _P, _P, _P, _P, _P, _I64]),
         "or_gram_relres": (_D, [_I, _I, _P, _P, _P]),
-        "or_sspcg": (_I, [_I64, _P, _P, _P, _P, _P, _I, _I, _D, _D, _D, _I, _I, _P, _P]),
+        "or_sspcg": (_I, [_I64, _P, _P, _P, _P, _P, _I, _I, _D, _D, _D, _I, _I, _D, _P, _P]),
         "or_pcg": (_I, [_I64, _P, _P, _P, _P, _P, _D, _I, _P, _P]),
         "or_sspcg_mixed": (_I, [_I64, _P, _P, _P, _P, _P, _I, _I, _D, _D, _D, _D, _I, _I,
                                 _P, _P]),
@@ -184,13 +185,17 @@ def gram_rect(Q, AZ):
     return B2
 
 
-def fgs(W, B, sweeps):
-    """nu FGS sweeps from zero.  B is (s,) or (s, nrhs).  Returns (X, status)."""
+def fgs(W, B, sweeps, sweep_tol=0.0):
+    """nu FGS sweeps from zero (fewer per column once ||m - W a|| <= sweep_tol
+    ||m|| when sweep_tol > 0).  B is (s,) or (s, nrhs).  Returns (X, status)."""
     W = _f64(W)
     vec = np.ndim(B) == 1
     B = _f64(B).reshape(W.shape[0], -1)
     X = np.empty_like(B)
-    st = lib().or_fgs(W.shape[0], B.shape[1], _p(W), _p(B), sweeps, _p(X))
+    if sweep_tol > 0.0:
+        st = lib().or_fgs_tol(W.shape[0], B.shape[1], _p(W), _p(B), sweeps, sweep_tol, _p(X))
+    else:
+        st = lib().or_fgs(W.shape[0], B.shape[1], _p(W), _p(B), sweeps, _p(X))
     return (X.reshape(-1) if vec else X), st
 
 
@@ -227,7 +232,7 @@ def gram_relres(W, B, X) -> float:
 
 
 def sspcg(A, b, x0=None, *, s, sweeps, interval, tol, max_outer=20000,
-          gram="fgs", history=False):
+          gram="fgs", sweep_tol=0.0, history=False):
     """Algorithm 1.  Returns (x, result dict[, history (k, 3)])."""
     b = _f64(b)
     x = np.zeros(A.n) if x0 is None else _f64(x0).copy()
@@ -235,7 +240,7 @@ def sspcg(A, b, x0=None, *, s, sweeps, interval, tol, max_outer=20000,
     res = Result()
     lib().or_sspcg(A.n, _p(A.row_ptr), _p(A.col), _p(A.val), _p(b), _p(x), s, sweeps,
                    interval[0], interval[1], tol, max_outer,
-                   1 if gram == "cholesky" else 0,
+                   1 if gram == "cholesky" else 0, sweep_tol,
                    None if hist is None else _p(hist), ctypes.byref(res))
     out = res.as_dict()
     if history:

@@ -211,7 +211,20 @@ void or_gram_rect(int64_t n, int s, const double* Q, const double* AZ, int64_t l
  * goes to X with the same layout.  W is read as symmetric from its lower
  * triangle.  Returns OR_BREAKDOWN if a diagonal entry is not positive and
  * OR_NONFINITE if W or B holds a non-finite value. */
+int or_fgs_tol(int s, int nrhs, const double* W, const double* B, int sweeps, double delta,
+               double* X);
+
 int or_fgs(int s, int nrhs, const double* W, const double* B, int sweeps, double* X)
+{
+    return or_fgs_tol(s, nrhs, W, B, sweeps, 0.0, X);
+}
+
+/* As or_fgs, but with delta > 0 a column stops sweeping as soon as its
+ * residual satisfies ||m - W a||_2 <= delta ||m||_2 (the practical accuracy
+ * criterion of Sec. 3, eq. cond:inexactKrylov1), checked before every sweep
+ * after the first; at most `sweeps` sweeps. */
+int or_fgs_tol(int s, int nrhs, const double* W, const double* B, int sweeps, double delta,
+               double* X)
 {
     for (int i = 0; i < s; ++i) {
         for (int j = 0; j <= i; ++j)
@@ -222,7 +235,20 @@ int or_fgs(int s, int nrhs, const double* W, const double* B, int sweeps, double
     }
     for (int c = 0; c < nrhs; ++c) {
         for (int i = 0; i < s; ++i) X[i * nrhs + c] = 0.0;
+        double mn = 0.0;
+        for (int i = 0; i < s; ++i) mn += B[i * nrhs + c] * B[i * nrhs + c];
+        mn = sqrt(mn);
         for (int v = 0; v < sweeps; ++v) {
+            if (delta > 0.0 && v > 0) {
+                double r2 = 0.0;
+                for (int i = 0; i < s; ++i) {
+                    double t = B[i * nrhs + c];
+                    for (int j = 0; j < s; ++j)
+                        t -= (j <= i ? W[i * s + j] : W[j * s + i]) * X[j * nrhs + c];
+                    r2 += t * t;
+                }
+                if (sqrt(r2) <= delta * mn) break;
+            }
             for (int i = 0; i < s; ++i) {
                 double t = B[i * nrhs + c];
                 for (int j = 0; j < i; ++j) t -= W[i * s + j] * X[j * nrhs + c];
@@ -339,7 +365,8 @@ double or_gram_relres(int s, int nrhs, const double* W, const double* B, const d
 /* ------------------------------------------------------------------ */
 
 /* Solves A x = b from x (in: x0, out: x).  gram = 0: FGS with `sweeps`
- * sweeps; gram = 1: Cholesky.  hist (optional, 3*max_outer doubles) receives
+ * sweeps (or fewer once a column meets sweep_tol > 0, see or_fgs_tol);
+ * gram = 1: Cholesky.  hist (optional, 3*max_outer doubles) receives
  * per outer iteration k: the relative residual after the x update,
  * eta_alpha and eta_beta (0 where no beta system was solved).
  * Stops when ||r|| <= tol ||b|| on the recursively updated residual.  If
@@ -347,7 +374,7 @@ double or_gram_relres(int s, int nrhs, const double* W, const double* B, const d
  * test no iteration is taken. */
 int or_sspcg(int64_t n, const int32_t* rp, const int32_t* col, const double* val,
              const double* b, double* x, int s, int sweeps, double lmin, double lmax,
-             double tol, int max_outer, int gram, double* hist, or_result* res)
+             double tol, int max_outer, int gram, double sweep_tol, double* hist, or_result* res)
 {
     memset(res, 0, sizeof(*res));
     if (n < 1 || s < 1 || s > 64 || (gram == 0 && sweeps < 1) || !(lmax > lmin)
@@ -390,7 +417,8 @@ int or_sspcg(int64_t n, const int32_t* rp, const int32_t* col, const double* val
     memcpy(AQ, P + ld, sizeof(double) * n * s);
     for (k = 0; k < max_outer; ++k) {
         or_gram(n, s, Q, AQ, P, ld, W, b1);        /* P(:,1) = r */
-        int st = gram ? or_chol_solve(s, 1, W, b1, al) : or_fgs(s, 1, W, b1, sweeps, al);
+        int st = gram ? or_chol_solve(s, 1, W, b1, al)
+                      : or_fgs_tol(s, 1, W, b1, sweeps, sweep_tol, al);
         if (st != OR_OK) { status = st; break; }
         or_xr_update(n, s, Q, AQ, al, ld, x, r);
         relres = or_nrm2(n, r) / nb;
@@ -404,7 +432,8 @@ int or_sspcg(int64_t n, const int32_t* rp, const int32_t* col, const double* val
         or_mpk(n, rp, col, val, dinv, r, s, lmin, lmax, Z, P, ld);
         /* AQ_new = P(:, 2:s+1) */
         or_gram_rect(n, s, Q, P + ld, ld, B2);
-        st = gram ? or_chol_solve(s, s, W, B2, be) : or_fgs(s, s, W, B2, sweeps, be);
+        st = gram ? or_chol_solve(s, s, W, B2, be)
+                  : or_fgs_tol(s, s, W, B2, sweeps, sweep_tol, be);
         if (hist) hist[3 * k + 2] = or_gram_relres(s, s, W, B2, be);
         if (st != OR_OK) { status = st; k += 1; break; }
         or_block_update(n, s, Z, Q, P + ld, AQ, be, ld);

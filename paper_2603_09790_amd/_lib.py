@@ -33,7 +33,8 @@ class Params(ctypes.Structure):
                 ("tol", ctypes.c_double), ("max_outer", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("inner_tol", ctypes.c_double),
                 ("max_refine", ctypes.c_int32), ("gram", ctypes.c_int32),
-                ("check_every", ctypes.c_int32), ("profile", ctypes.c_int32)]
+                ("check_every", ctypes.c_int32), ("profile", ctypes.c_int32),
+                ("sweep_tol", ctypes.c_double)]
 
 
 class Result(ctypes.Structure):
@@ -94,7 +95,7 @@ def lib() -> ctypes.CDLL:
         "sspcg_block_update_gram": (ctypes.c_int, [I64, I32, I32, P, P, P, P, P, P, I64, P, P,
                                                    P, SZ, P]),
         "sspcg_gram_rect": (ctypes.c_int, [I64, I32, I32, P, P, I64, P, P, SZ, P]),
-        "sspcg_fgs": (ctypes.c_int, [I32, I32, P, P, I32, I32, P, P, P]),
+        "sspcg_fgs": (ctypes.c_int, [I32, I32, P, P, I32, D, I32, P, P, P]),
         "sspcg_xr_update": (ctypes.c_int, [P, I32, I32, P, P, P, I64, P, P, P, P, P, SZ, P]),
         "sspcg_csr_value_grad": (ctypes.c_int, [P, P, P, P, P]),
         "sspcg_diffusion7_assemble": (ctypes.c_int, [P, P, P, P]),

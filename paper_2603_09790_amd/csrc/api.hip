@@ -133,6 +133,7 @@ int check_params(const sspcg_matrix* A, const sspcg_params* p, bool pcg)
     if (pcg) return SSPCG_OK;
     if (p->s < 1 || p->s > SSPCG_MAX_S) return arg_error("s must be in 1..16");
     if (p->sweeps < 1 || p->sweeps > 1000) return arg_error("sweeps must be in 1..1000");
+    if (!(p->sweep_tol >= 0.0) || !(p->sweep_tol < 1.0)) return arg_error("sweep_tol must be in [0,1)");
     if (!(p->lambda_min >= 0.0) || !(p->lambda_max > p->lambda_min) || !std::isfinite(p->lambda_max))
         return arg_error("need 0 <= lambda_min < lambda_max");
     if (p->gram != SSPCG_GRAM_FGS && p->gram != SSPCG_GRAM_CHOLESKY)
@@ -338,7 +339,8 @@ int run_sspcg(const sspcg_matrix* A, const sspcg_params* p, const Workspace& w, 
         rc = launch_update_gram<T>(n, s, Z, Q, AZ, AQ, nullptr, r, ld, part, &G, ctrl, st);
     tm.start_mark(2, st);
     if (rc == SSPCG_OK)
-        rc = launch_fgs_step(s, 0, part, G, Wbuf, alpha, p->sweeps, p->gram, ctrl, dhist, st);
+        rc = launch_fgs_step(s, 0, part, G, Wbuf, alpha, p->sweeps, p->sweep_tol, p->gram, ctrl,
+                             dhist, st);
     tm.start_mark(3, st);
     if (rc != SSPCG_OK) return rc;
     auto step = [&](int64_t k) -> int {
@@ -353,12 +355,14 @@ int run_sspcg(const sspcg_matrix* A, const sspcg_params* p, const Workspace& w, 
         if (e == SSPCG_OK) e = launch_gram_rect<T>(n, s, Q, AZ, ld, part, &g, ctrl, st);
         tm.mark(k, 4, st);
         if (e == SSPCG_OK)
-            e = launch_fgs_step(s, 1, part, g, Wbuf, beta, p->sweeps, p->gram, ctrl, dhist, st);
+            e = launch_fgs_step(s, 1, part, g, Wbuf, beta, p->sweeps, p->sweep_tol, p->gram, ctrl,
+                                dhist, st);
         tm.mark(k, 5, st);
         if (e == SSPCG_OK) e = launch_update_gram<T>(n, s, Z, Q, AZ, AQ, beta, r, ld, part, &g, ctrl, st);
         tm.mark(k, 6, st);
         if (e == SSPCG_OK)
-            e = launch_fgs_step(s, 0, part, g, Wbuf, alpha, p->sweeps, p->gram, ctrl, dhist, st);
+            e = launch_fgs_step(s, 0, part, g, Wbuf, alpha, p->sweeps, p->sweep_tol, p->gram, ctrl,
+                                dhist, st);
         tm.mark(k, 7, st);
         return e;
     };
@@ -682,6 +686,7 @@ void sspcg_default_params(sspcg_params* p)
     p->gram = SSPCG_GRAM_FGS;
     p->check_every = 8;
     p->profile = 0;
+    p->sweep_tol = 0.0;
 }
 
 int sspcg_matrix_create(int32_t n, int32_t nnz, const int32_t* row_ptr, const int32_t* col,
@@ -1013,16 +1018,19 @@ int sspcg_gram_rect(int64_t n, int32_t s, int32_t dtype, const void* Q, const vo
 }
 
 int sspcg_fgs(int32_t s, int32_t nrhs, const double* W, const double* B, int32_t sweeps,
-              int32_t gram_solver, double* X, int32_t* status, sspcg_stream stream)
+              double sweep_tol, int32_t gram_solver, double* X, int32_t* status,
+              sspcg_stream stream)
 {
     API_TRY
+    if (!(sweep_tol >= 0.0) || !(sweep_tol < 1.0)) return arg_error("sweep_tol must be in [0,1)");
     if (s < 1 || s > SSPCG_MAX_S) return arg_error("s must be in 1..16");
     if (nrhs < 1 || nrhs > 4096) return arg_error("nrhs must be in 1..4096");
     if (sweeps < 1 || sweeps > 100000) return arg_error("sweeps out of range");
     if (gram_solver != SSPCG_GRAM_FGS && gram_solver != SSPCG_GRAM_CHOLESKY)
         return arg_error("unknown gram solver");
     if (!W || !B || !X || !status) return arg_error("NULL pointer");
-    return launch_fgs_direct(s, nrhs, W, B, sweeps, gram_solver, X, status, as_stream(stream));
+    return launch_fgs_direct(s, nrhs, W, B, sweeps, sweep_tol, gram_solver, X, status,
+                             as_stream(stream));
     API_CATCH
 }
 

@@ -50,11 +50,28 @@ __device__ inline int cholesky(const double (&W)[S][S], double (&L)[S][S])
     return SSPCG_OK;
 }
 
-// Column c of X from column c of B: FGS sweeps or the Cholesky solve.
+// ||b - W x||_2 for column c (W mirrored from its lower triangle).
+template <int S>
+__device__ inline double column_residual(const double (&W)[S][S], const double (&B)[S][S], int c,
+                                         const double (&x)[S])
+{
+    double r2 = 0.0;
+#pragma unroll
+    for (int i = 0; i < S; ++i) {
+        double t = B[i][c];
+#pragma unroll
+        for (int j = 0; j < S; ++j) t -= (j <= i ? W[i][j] : W[j][i]) * x[j];
+        r2 += t * t;
+    }
+    return sqrt(r2);
+}
+
+// Column c of X from column c of B: FGS sweeps (at most `sweeps`; with
+// delta > 0 stopping once ||b - W x|| <= delta ||b||) or the Cholesky solve.
 template <int S>
 __device__ inline void solve_column(const double (&W)[S][S], const double (&L)[S][S],
-                                    const double (&B)[S][S], int c, int sweeps, int solver,
-                                    double (&X)[S][S])
+                                    const double (&B)[S][S], int c, int sweeps, double delta,
+                                    int solver, double (&X)[S][S])
 {
     double x[S];
     if (solver == SSPCG_GRAM_CHOLESKY) {
@@ -75,7 +92,14 @@ __device__ inline void solve_column(const double (&W)[S][S], const double (&L)[S
     } else {
 #pragma unroll
         for (int i = 0; i < S; ++i) x[i] = 0.0;
+        double bn = 0.0;
+        if (delta > 0.0) {
+#pragma unroll
+            for (int i = 0; i < S; ++i) bn += B[i][c] * B[i][c];
+            bn = sqrt(bn);
+        }
         for (int v = 0; v < sweeps; ++v) {
+            if (delta > 0.0 && v > 0 && column_residual<S>(W, B, c, x) <= delta * bn) break;
 #pragma unroll
             for (int i = 0; i < S; ++i) {
                 double t = B[i][c];
@@ -113,7 +137,8 @@ template <int S>
 __global__ __launch_bounds__(kFinBlock) void k_fgs_step(int which, const double* __restrict__ partials,
                                                         int G, double* __restrict__ Wbuf,
                                                         double* __restrict__ out, int sweeps,
-                                                        int solver, Ctrl* __restrict__ ctrl,
+                                                        double delta, int solver,
+                                                        Ctrl* __restrict__ ctrl,
                                                         double* __restrict__ hist)
 {
     if (ctrl->done) return;
@@ -151,7 +176,7 @@ __global__ __launch_bounds__(kFinBlock) void k_fgs_step(int which, const double*
     }
     __syncthreads();
     if (st == SSPCG_OK && (int)threadIdx.x < nrhs)
-        solve_column<S>(W, L, B, threadIdx.x, sweeps, solver, X);
+        solve_column<S>(W, L, B, threadIdx.x, sweeps, delta, solver, X);
     __syncthreads();
     if (threadIdx.x == 0) {
         if (st != SSPCG_OK) {
@@ -176,7 +201,8 @@ __global__ __launch_bounds__(kFinBlock) void k_fgs_step(int which, const double*
 template <int S>
 __global__ __launch_bounds__(kWave) void k_fgs_direct(int nrhs, const double* __restrict__ Wd,
                                                       const double* __restrict__ Bd, int sweeps,
-                                                      int solver, double* __restrict__ Xd,
+                                                      double delta, int solver,
+                                                      double* __restrict__ Xd,
                                                       int32_t* __restrict__ status)
 {
     __shared__ double W[S][S], L[S][S], B[S][S], X[S][S];
@@ -202,7 +228,7 @@ __global__ __launch_bounds__(kWave) void k_fgs_direct(int nrhs, const double* __
         }
         __syncthreads();
         if (st == SSPCG_OK && (int)threadIdx.x < nc)
-            solve_column<S>(W, L, B, threadIdx.x, sweeps, solver, X);
+            solve_column<S>(W, L, B, threadIdx.x, sweeps, delta, solver, X);
         __syncthreads();
         if (st == SSPCG_OK && threadIdx.x == 0)
             for (int i = 0; i < S; ++i)
@@ -275,13 +301,13 @@ __global__ __launch_bounds__(kFinBlock) void k_gram_out(int s, int which,
     X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16)
 
 int launch_fgs_step(int s, int which, const double* partials, int G, double* Wbuf, double* out,
-                    int sweeps, int solver, Ctrl* ctrl, double* hist, hipStream_t st)
+                    int sweeps, double delta, int solver, Ctrl* ctrl, double* hist, hipStream_t st)
 {
     switch (s) {
 #define X(S)                                                                                   \
     case S:                                                                                    \
         hipLaunchKernelGGL((k_fgs_step<S>), dim3(1), dim3(kFinBlock), 0, st, which, partials, \
-                           G, Wbuf, out, sweeps, solver, ctrl, hist);                          \
+                           G, Wbuf, out, sweeps, delta, solver, ctrl, hist);                   \
         break;
         SSPCG_S_CASES(X)
 #undef X
@@ -293,14 +319,14 @@ int launch_fgs_step(int s, int which, const double* partials, int G, double* Wbu
     return SSPCG_OK;
 }
 
-int launch_fgs_direct(int s, int nrhs, const double* W, const double* B, int sweeps, int solver,
-                      double* X, int32_t* status, hipStream_t st)
+int launch_fgs_direct(int s, int nrhs, const double* W, const double* B, int sweeps, double delta,
+                      int solver, double* X, int32_t* status, hipStream_t st)
 {
     switch (s) {
 #define X(S)                                                                                  \
     case S:                                                                                   \
         hipLaunchKernelGGL((k_fgs_direct<S>), dim3(1), dim3(kWave), 0, st, nrhs, W, B, sweeps, \
-                           solver, X, status);                                                \
+                           delta, solver, X, status);                                         \
         break;
         SSPCG_S_CASES(X)
 #undef X

@@ -96,9 +96,10 @@ int launch_fill(int64_t n, T* x, T v, hipStream_t st);
 //   which = 0: alpha system (partials hold W lower + b1; W is also stored)
 //   which = 1: beta system (partials hold Q^T AZ; W from Wbuf)
 int launch_fgs_step(int s, int which, const double* partials, int G, double* Wbuf, double* out,
-                    int sweeps, int solver, Ctrl* ctrl, double* hist, hipStream_t st);
-int launch_fgs_direct(int s, int nrhs, const double* W, const double* B, int sweeps, int solver,
-                      double* X, int32_t* status, hipStream_t st);
+                    int sweeps, double delta, int solver, Ctrl* ctrl, double* hist,
+                    hipStream_t st);
+int launch_fgs_direct(int s, int nrhs, const double* W, const double* B, int sweeps, double delta,
+                      int solver, double* X, int32_t* status, hipStream_t st);
 // Finishes ||r||^2 for outer iteration k: relres, stop test, history.
 int launch_norm_step(const double* partials, int G, int64_t k, Ctrl* ctrl, double* hist,
                      hipStream_t st);

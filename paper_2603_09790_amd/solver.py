@@ -117,7 +117,7 @@ class Matrix:
 
 
 def _params(s, sweeps, interval, tol, precision, gram, max_outer, inner_tol, max_refine,
-            check_every, profile=False) -> L.Params:
+            check_every, profile=False, sweep_tol=0.0) -> L.Params:
     p = L.Params()
     L.lib().sspcg_default_params(ctypes.byref(p))
     p.s = int(s)
@@ -131,6 +131,7 @@ def _params(s, sweeps, interval, tol, precision, gram, max_outer, inner_tol, max
     p.gram = {"fgs": L.GRAM_FGS, "cholesky": L.GRAM_CHOLESKY}[gram]
     p.check_every = int(check_every)
     p.profile = 1 if profile else 0
+    p.sweep_tol = float(sweep_tol)
     return p
 
 
@@ -143,7 +144,8 @@ def solve(A: Matrix, b: torch.Tensor, x0: torch.Tensor | None = None, *, s: int 
           sweeps: int = 2, interval=(0.0, 2.0), tol: float = 1e-8, precision: str = "fp64",
           gram: str = "fgs", max_outer: int = 20000, inner_tol: float = 1e-4,
           max_refine: int = 20, check_every: int = 8, history: bool = False,
-          profile: bool = False, out: torch.Tensor | None = None, raise_on_error: bool = True):
+          profile: bool = False, sweep_tol: float = 0.0, out: torch.Tensor | None = None,
+          raise_on_error: bool = True):
     """s-step PCG (Algorithm 1) on A x = b.  Returns (x, info).
 
     info['history'] (when history=True): per outer iteration
@@ -152,7 +154,7 @@ def solve(A: Matrix, b: torch.Tensor, x0: torch.Tensor | None = None, *, s: int 
     launches per phase, from HIP events around every phase.
     """
     p = _params(s, sweeps, interval, tol, precision, gram, max_outer, inner_tol, max_refine,
-                check_every, profile)
+                check_every, profile, sweep_tol)
     dev = A.device
     b = _on(b, dev, torch.float64)
     if out is None:
@@ -274,7 +276,8 @@ def gram_rect(n: int, Q, AZ):
     return B2
 
 
-def fgs(W: torch.Tensor, B: torch.Tensor, sweeps: int, solver: str = "fgs"):
+def fgs(W: torch.Tensor, B: torch.Tensor, sweeps: int, solver: str = "fgs",
+        sweep_tol: float = 0.0):
     """FGS (or Cholesky) solve of W X = B on the device.  Returns (X, status)."""
     s = W.shape[0]
     vec = B.dim() == 1
@@ -283,6 +286,7 @@ def fgs(W: torch.Tensor, B: torch.Tensor, sweeps: int, solver: str = "fgs"):
     status = torch.zeros(1, dtype=torch.int32, device=W.device)
     with torch.cuda.device(W.device):
         L.check(L.lib().sspcg_fgs(s, Bm.shape[1], _p(W.contiguous()), _p(Bm), sweeps,
+                                  float(sweep_tol),
                                   {"fgs": L.GRAM_FGS, "cholesky": L.GRAM_CHOLESKY}[solver],
                                   _p(X), _p(status), _stream(W.device)), "sspcg_fgs")
     return (X.reshape(-1) if vec else X), int(status.item())

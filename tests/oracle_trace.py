@@ -12,7 +12,7 @@ import numpy as np
 import oracle
 
 
-def trace(A, b, *, s, sweeps, interval, tol, max_outer, x0=None, gram="fgs"):
+def trace(A, b, *, s, sweeps, interval, tol, max_outer, x0=None, gram="fgs", sweep_tol=0.0):
     """Returns (x, status, states).
 
     states[k] is a dict holding, at the start of outer iteration k (before
@@ -28,7 +28,7 @@ def trace(A, b, *, s, sweeps, interval, tol, max_outer, x0=None, gram="fgs"):
     Q, AQ = Z.copy(), P[1:].copy()
     states = []
     solve = (lambda W, B: oracle.chol_solve(W, B)) if gram == "cholesky" else \
-        (lambda W, B: oracle.fgs(W, B, sweeps))
+        (lambda W, B: oracle.fgs(W, B, sweeps, sweep_tol))
     status = oracle.NOT_CONVERGED
     for k in range(max_outer):
         st = dict(k=k, x=x.copy(), r=r.copy(), Z=Z.copy(), P=P.copy(), Q=Q.copy(), AQ=AQ.copy())

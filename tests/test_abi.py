@@ -94,11 +94,12 @@ def test_host_side_argument_errors():
     assert lib.sspcg_workspace_bytes(None, ctypes.byref(p), ctypes.byref(sz)) == L.ERR_ARG
     X = ctypes.c_void_p(256)
     st = ctypes.c_void_p(256)
-    assert lib.sspcg_fgs(0, 1, X, X, 2, 0, X, st, None) == L.ERR_ARG
-    assert lib.sspcg_fgs(17, 1, X, X, 2, 0, X, st, None) == L.ERR_ARG
-    assert lib.sspcg_fgs(4, 1, X, X, 0, 0, X, st, None) == L.ERR_ARG
-    assert lib.sspcg_fgs(4, 1, X, X, 2, 7, X, st, None) == L.ERR_ARG
-    assert lib.sspcg_fgs(4, 1, None, X, 2, 0, X, st, None) == L.ERR_ARG
+    assert lib.sspcg_fgs(0, 1, X, X, 2, 0.0, 0, X, st, None) == L.ERR_ARG
+    assert lib.sspcg_fgs(17, 1, X, X, 2, 0.0, 0, X, st, None) == L.ERR_ARG
+    assert lib.sspcg_fgs(4, 1, X, X, 0, 0.0, 0, X, st, None) == L.ERR_ARG
+    assert lib.sspcg_fgs(4, 1, X, X, 2, 0.0, 7, X, st, None) == L.ERR_ARG
+    assert lib.sspcg_fgs(4, 1, None, X, 2, 0.0, 0, X, st, None) == L.ERR_ARG
+    assert lib.sspcg_fgs(4, 1, X, X, 2, -1.0, 0, X, st, None) == L.ERR_ARG
     assert lib.sspcg_gram_rect(0, 4, 0, X, X, 1, X, X, 1 << 30, None) == L.ERR_ARG
     assert lib.sspcg_gram_rect(100, 4, 0, X, X, 50, X, X, 1 << 30, None) == L.ERR_ARG
     assert lib.sspcg_gram_rect(100, 4, 0, X, X, 128, X, X, 16, None) == L.ERR_WORKSPACE

@@ -373,3 +373,17 @@ def test_stencil_slices_use_shared_offsets():
     assert A.nnz <= info["slots"] <= 27 * N**3
     # values only: 8 bytes per slot plus small metadata, no column indices
     assert info["device_bytes"] < 8 * info["slots"] + 40 * A.n
+
+
+@pytest.mark.parametrize("key", KEYS)
+def test_fgs_sweep_tol_on_oracle_systems(traced, key):
+    _, _, states, _ = traced[key]
+    st = states[3]
+    for d in (1e-1, 1e-4):
+        a, code = P.fgs(gpu(st["W"]), gpu(st["b1"]), 300, sweep_tol=d)
+        ar, _ = oracle.fgs(st["W"], st["b1"], 300, sweep_tol=d)
+        assert code == 0
+        assert np.abs(host(a) - ar).max() <= 1e-10 * np.abs(ar).max()
+        B, code = P.fgs(gpu(st["W"]), gpu(st["B2"]), 300, sweep_tol=d)
+        Br, _ = oracle.fgs(st["W"], st["B2"], 300, sweep_tol=d)
+        assert np.abs(host(B) - Br).max() <= 1e-10 * np.abs(Br).max()

@@ -280,3 +280,16 @@ def test_sparse_solve_value_and_rhs_gradient():
     assert rel(bb.grad.cpu().numpy(), lam) <= 1e-9
     rows = np.repeat(np.arange(A.n), np.diff(A.row_ptr))
     assert rel(val.grad.cpu().numpy(), -lam[rows] * xs[A.col]) <= 1e-9
+
+
+@pytest.mark.parametrize("sweep_tol", [1e-2, 1e-6])
+def test_adaptive_sweeps(poisson5, sweep_tol):
+    w = poisson5
+    x, info = run(w, s=4, sweeps=200, sweep_tol=sweep_tol, tol=1e-8, history=True)
+    xo, ro, ho = oracle.sspcg(w["A"], w["b"], s=4, sweeps=200, interval=w["interval"], tol=1e-8,
+                              sweep_tol=sweep_tol, history=True)
+    assert info["status"] == ro["status"] == 0
+    assert abs(info["outer_iters"] - ro["iters"]) <= 2
+    assert rel(x, xo) <= 1e-8
+    # the reduced systems meet the criterion (or the sweep cap was reached)
+    assert np.all(info["history"][:, 1] <= sweep_tol * (1 + 1e-6))

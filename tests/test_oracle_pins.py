@@ -446,3 +446,41 @@ def test_gradient_chain_matches_autograd_and_finite_differences():
 
     fd = (loss(theta + h * u) - loss(theta - h * u)) / (2 * h)
     assert abs(fd - g @ u) <= 1e-6 * abs(g @ u) + 1e-12
+
+
+# ------------------------------------------------------ adaptive sweep count
+def test_fgs_sweep_tol_stops_at_first_sweep_meeting_criterion():
+    """With sweep_tol = d, each column takes the fewest sweeps (up to the cap)
+    after which ||m - W a|| <= d ||m|| (the criterion of Sec. 3); d = 0 is
+    the fixed-sweep FGS."""
+    s = 8
+    W = random_spd(s, seed=31, cond=30.0)
+    B = np.random.default_rng(32).normal(size=(s, 3))
+    X0, _ = oracle.fgs(W, B, 7)
+    X0b, _ = oracle.fgs(W, B, 7, sweep_tol=0.0)
+    assert np.array_equal(X0, X0b)
+    for d in (1e-1, 1e-3, 1e-6):
+        X, st = oracle.fgs(W, B, 500, sweep_tol=d)
+        assert st == oracle.OK
+        for c in range(3):
+            m = B[:, c]
+            res = lambda a: np.linalg.norm(m - W @ a)
+            nu = next(v for v in range(1, 501)
+                      if res(oracle.fgs(W, m, v)[0]) <= d * np.linalg.norm(m))
+            assert np.array_equal(X[:, c], oracle.fgs(W, m, nu)[0])
+            if nu > 1:
+                assert res(oracle.fgs(W, m, nu - 1)[0]) > d * np.linalg.norm(m)
+    # the cap still applies
+    Xc, _ = oracle.fgs(W, B, 2, sweep_tol=1e-12)
+    assert np.array_equal(Xc, oracle.fgs(W, B, 2)[0])
+
+
+def test_sspcg_with_tight_sweep_tol_matches_cholesky():
+    w = si.workload("poisson5", N=24)
+    A, b = w["A"], w["b"]
+    _, rc, hc = oracle.sspcg(A, b, s=4, sweeps=1, interval=w["interval"], tol=1e-10,
+                             gram="cholesky", history=True)
+    _, rf, hf = oracle.sspcg(A, b, s=4, sweeps=1000, interval=w["interval"], tol=1e-10,
+                             sweep_tol=1e-13, history=True)
+    assert rc["iters"] == rf["iters"]
+    assert np.allclose(hf[:, 0], hc[:, 0], rtol=1e-6)
