@@ -67,6 +67,11 @@ typedef enum {
     SSPCG_GRAM_CHOLESKY = 1     /* exact solve by Cholesky (the paper's comparison) */
 } sspcg_gram_solver;
 
+typedef enum {
+    SSPCG_BASIS_CHEBYSHEV = 0,  /* z_j = T_{j-1}(alpha M^{-1}A - sigma I) M^{-1} r (Sec. 2) */
+    SSPCG_BASIS_MONOMIAL = 1    /* z_j = (M^{-1}A)^{j-1} M^{-1} r, the ill-conditioned contrast */
+} sspcg_basis;
+
 /* Element type of vector arguments of the kernel-level calls. */
 typedef enum { SSPCG_F64 = 0, SSPCG_F32 = 1 } sspcg_dtype;
 
@@ -92,6 +97,8 @@ typedef struct {
     double sweep_tol;           /* 0: exactly `sweeps` FGS sweeps.  > 0: each right-hand side
                                    stops sweeping once ||m - W a|| <= sweep_tol ||m|| (the
                                    accuracy criterion of Sec. 3), after at most `sweeps` */
+    int32_t basis;              /* sspcg_basis of the Krylov block */
+    int32_t reserved;
 } sspcg_params;
 
 /* Outcome of a solve (host struct filled by the solve calls). */
@@ -208,9 +215,10 @@ int sspcg_spmv(const sspcg_matrix* A, int32_t dtype, const void* x, void* y, ssp
  * (device, n x s and n x (s+1), leading dimension ld, dtype elements) with
  * z_1 = M^{-1} r, z_{q+1} the Chebyshev three-term recurrence in
  * alpha M^{-1}A - sigma I (first step the T_1 one), p_1 = r, p_{q+1} = A z_q;
- * alpha = 2/(lmax-lmin), sigma = (lmax+lmin)/(lmax-lmin), gamma = 1. */
+ * alpha = 2/(lmax-lmin), sigma = (lmax+lmin)/(lmax-lmin), gamma = 1.  With
+ * basis = SSPCG_BASIS_MONOMIAL, z_{q+1} = M^{-1} p_{q+1} (interval unused). */
 int sspcg_mpk(const sspcg_matrix* A, int32_t dtype, const void* r, int32_t s, double lmin,
-              double lmax, void* Z, void* P, int64_t ld, sspcg_stream stream);
+              double lmax, int32_t basis, void* Z, void* P, int64_t ld, sspcg_stream stream);
 
 /* Block update fused with the Gram reduction of Algorithm 1:
  *   if beta != NULL: Q <- Z + Q beta and AQ <- AZ + AQ beta (in place);

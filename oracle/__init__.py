@@ -67,6 +67,7 @@ def lib():
         "or_spmv_f32": (None, [_I64, _P, _P, _P, _P, _P]),
         "or_diagonal": (_I64, [_I64, _P, _P, _P, _P]),
         "or_mpk": (None, [_I64, _P, _P, _P, _P, _P, _I, _D, _D, _P, _P, _I64]),
+        "or_mpk_basis": (None, [_I64, _P, _P, _P, _P, _P, _I, _D, _D, _I, _P, _P, _I64]),
         "or_mpk_f32": (None, [_I64, _P, _P, _P, _P, _P, _I, _D, _D, _P, _P, _I64]),
         "or_gram": (None, [_I64, _I, _P, _P, _P, _I64, _P, _P]),
         "or_gram_f32": (None, [_I64, _I, _P, _P, _P, _I64, _P, _P]),
@@ -80,7 +81,7 @@ def lib():
         "or_block_update": (None, [_I64, _I, _P, _P, _P, _P, _P, _I64]),
         "or_block_update_f32": (None, [_I64, _I, _P, _P, _P, _P, _P, _I64]),
         "or_gram_relres": (_D, [_I, _I, _P, _P, _P]),
-        "or_sspcg": (_I, [_I64, _P, _P, _P, _P, _P, _I, _I, _D, _D, _D, _I, _I, _D, _P, _P]),
+        "or_sspcg": (_I, [_I64, _P, _P, _P, _P, _P, _I, _I, _D, _D, _D, _I, _I, _D, _I, _P, _P]),
         "or_pcg": (_I, [_I64, _P, _P, _P, _P, _P, _D, _I, _P, _P]),
         "or_sspcg_mixed": (_I, [_I64, _P, _P, _P, _P, _P, _I, _I, _D, _D, _D, _D, _I, _I,
                                 _P, _P]),
@@ -139,13 +140,17 @@ def jacobi_inverse(A) -> np.ndarray:
     return 1.0 / d
 
 
-def mpk(A, dinv, r, s, interval):
+def mpk(A, dinv, r, s, interval, basis="chebyshev"):
     """Algorithm 2: returns Z (s, n) and P (s+1, n)."""
     dinv, r = _f64(dinv), _f64(r)
     Z = np.empty((s, A.n))
     P = np.empty((s + 1, A.n))
-    lib().or_mpk(A.n, _p(A.row_ptr), _p(A.col), _p(A.val), _p(dinv), _p(r), s,
-                 interval[0], interval[1], _p(Z), _p(P), A.n)
+    if basis == "chebyshev":
+        lib().or_mpk(A.n, _p(A.row_ptr), _p(A.col), _p(A.val), _p(dinv), _p(r), s,
+                     interval[0], interval[1], _p(Z), _p(P), A.n)
+    else:
+        lib().or_mpk_basis(A.n, _p(A.row_ptr), _p(A.col), _p(A.val), _p(dinv), _p(r), s,
+                           interval[0], interval[1], 1, _p(Z), _p(P), A.n)
     return Z, P
 
 
@@ -232,7 +237,7 @@ def gram_relres(W, B, X) -> float:
 
 
 def sspcg(A, b, x0=None, *, s, sweeps, interval, tol, max_outer=20000,
-          gram="fgs", sweep_tol=0.0, history=False):
+          gram="fgs", sweep_tol=0.0, basis="chebyshev", history=False):
     """Algorithm 1.  Returns (x, result dict[, history (k, 3)])."""
     b = _f64(b)
     x = np.zeros(A.n) if x0 is None else _f64(x0).copy()
@@ -241,6 +246,7 @@ def sspcg(A, b, x0=None, *, s, sweeps, interval, tol, max_outer=20000,
     lib().or_sspcg(A.n, _p(A.row_ptr), _p(A.col), _p(A.val), _p(b), _p(x), s, sweeps,
                    interval[0], interval[1], tol, max_outer,
                    1 if gram == "cholesky" else 0, sweep_tol,
+                   0 if basis == "chebyshev" else 1,
                    None if hist is None else _p(hist), ctypes.byref(res))
     out = res.as_dict()
     if history:

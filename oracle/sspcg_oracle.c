@@ -139,9 +139,23 @@ static void basis_info(double lmin, double lmax, double* a, double* sg, double* 
  *   p_2 = A z_1, zp_2 = alpha p_2 - sigma zp_1                (T_1 step)
  *   p_{q+1} = A z_q, zp_{q+1} = 2 alpha p_{q+1} - 2 sigma zp_q - gamma zp_{q-1}
  *   z_{q+1} = M^{-1} zp_{q+1};  finally p_{s+1} = A z_s. */
+void or_mpk_basis(int64_t n, const int32_t* rp, const int32_t* col, const double* val,
+                  const double* dinv, const double* r, int s, double lmin, double lmax,
+                  int basis, double* Z, double* P, int64_t ld);
+
 void or_mpk(int64_t n, const int32_t* rp, const int32_t* col, const double* val,
             const double* dinv, const double* r, int s, double lmin, double lmax,
             double* Z, double* P, int64_t ld)
+{
+    or_mpk_basis(n, rp, col, val, dinv, r, s, lmin, lmax, 0, Z, P, ld);
+}
+
+/* basis = 0: the Chebyshev recurrence above.  basis = 1: the monomial block
+ * of the paper's introduction, z_{q+1} = M^{-1} A z_q, i.e. zp_{q+1} =
+ * p_{q+1} (the contrast the Chebyshev basis is chosen against). */
+void or_mpk_basis(int64_t n, const int32_t* rp, const int32_t* col, const double* val,
+                  const double* dinv, const double* r, int s, double lmin, double lmax,
+                  int basis, double* Z, double* P, int64_t ld)
 {
     double al, sg, gm;
     basis_info(lmin, lmax, &al, &sg, &gm);
@@ -154,7 +168,15 @@ void or_mpk(int64_t n, const int32_t* rp, const int32_t* col, const double* val,
         ZP(1)[i] = PC(1)[i];
         ZC(1)[i] = dinv[i] * ZP(1)[i];
     }
-    if (s > 1) {
+    if (basis == 1) {
+        for (int q = 1; q <= s - 1; ++q) {
+            or_spmv(n, rp, col, val, ZC(q), PC(q + 1));
+            for (int64_t i = 0; i < n; ++i) {
+                ZP(q + 1)[i] = PC(q + 1)[i];
+                ZC(q + 1)[i] = dinv[i] * ZP(q + 1)[i];
+            }
+        }
+    } else if (s > 1) {
         or_spmv(n, rp, col, val, ZC(1), PC(2));
         for (int64_t i = 0; i < n; ++i) {
             ZP(2)[i] = al * PC(2)[i] - sg * ZP(1)[i];
@@ -366,7 +388,7 @@ double or_gram_relres(int s, int nrhs, const double* W, const double* B, const d
 
 /* Solves A x = b from x (in: x0, out: x).  gram = 0: FGS with `sweeps`
  * sweeps (or fewer once a column meets sweep_tol > 0, see or_fgs_tol);
- * gram = 1: Cholesky.  hist (optional, 3*max_outer doubles) receives
+ * gram = 1: Cholesky.  basis: 0 Chebyshev, 1 monomial (or_mpk_basis).  hist (optional, 3*max_outer doubles) receives
  * per outer iteration k: the relative residual after the x update,
  * eta_alpha and eta_beta (0 where no beta system was solved).
  * Stops when ||r|| <= tol ||b|| on the recursively updated residual.  If
@@ -374,7 +396,8 @@ double or_gram_relres(int s, int nrhs, const double* W, const double* B, const d
  * test no iteration is taken. */
 int or_sspcg(int64_t n, const int32_t* rp, const int32_t* col, const double* val,
              const double* b, double* x, int s, int sweeps, double lmin, double lmax,
-             double tol, int max_outer, int gram, double sweep_tol, double* hist, or_result* res)
+             double tol, int max_outer, int gram, double sweep_tol, int basis, double* hist,
+             or_result* res)
 {
     memset(res, 0, sizeof(*res));
     if (n < 1 || s < 1 || s > 64 || (gram == 0 && sweeps < 1) || !(lmax > lmin)
@@ -412,7 +435,7 @@ int or_sspcg(int64_t n, const int32_t* rp, const int32_t* col, const double* val
     int status = OR_NOT_CONVERGED, k = 0;
     if (relres <= tol) { status = OR_OK; goto done; }
 
-    or_mpk(n, rp, col, val, dinv, r, s, lmin, lmax, Z, P, ld);
+    or_mpk_basis(n, rp, col, val, dinv, r, s, lmin, lmax, basis, Z, P, ld);
     memcpy(Q, Z, sizeof(double) * n * s);
     memcpy(AQ, P + ld, sizeof(double) * n * s);
     for (k = 0; k < max_outer; ++k) {
@@ -429,7 +452,7 @@ int or_sspcg(int64_t n, const int32_t* rp, const int32_t* col, const double* val
         }
         if (!isfinite(relres)) { status = OR_NONFINITE; k += 1; break; }
         if (relres <= tol) { status = OR_OK; k += 1; break; }
-        or_mpk(n, rp, col, val, dinv, r, s, lmin, lmax, Z, P, ld);
+        or_mpk_basis(n, rp, col, val, dinv, r, s, lmin, lmax, basis, Z, P, ld);
         /* AQ_new = P(:, 2:s+1) */
         or_gram_rect(n, s, Q, P + ld, ld, B2);
         st = gram ? or_chol_solve(s, s, W, B2, be)

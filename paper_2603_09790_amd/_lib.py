@@ -12,6 +12,7 @@ ERR_ARG, ERR_HIP, ERR_BREAKDOWN, ERR_WORKSPACE, ERR_NONFINITE, ERR_UNSUPPORTED =
 FP64, MIXED = 0, 1
 GRAM_FGS, GRAM_CHOLESKY = 0, 1
 F64, F32 = 0, 1
+BASIS = {"chebyshev": 0, "monomial": 1}
 MATRIX_FP32 = 1
 MAX_S = 16
 
@@ -34,7 +35,8 @@ class Params(ctypes.Structure):
                 ("precision", ctypes.c_int32), ("inner_tol", ctypes.c_double),
                 ("max_refine", ctypes.c_int32), ("gram", ctypes.c_int32),
                 ("check_every", ctypes.c_int32), ("profile", ctypes.c_int32),
-                ("sweep_tol", ctypes.c_double)]
+                ("sweep_tol", ctypes.c_double), ("basis", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class Result(ctypes.Structure):
@@ -91,7 +93,7 @@ def lib() -> ctypes.CDLL:
                                            ctypes.POINTER(Result), P]),
         "sspcg_kernel_work_bytes": (SZ, [I32]),
         "sspcg_spmv": (ctypes.c_int, [P, I32, P, P, P]),
-        "sspcg_mpk": (ctypes.c_int, [P, I32, P, I32, D, D, P, P, I64, P]),
+        "sspcg_mpk": (ctypes.c_int, [P, I32, P, I32, D, D, I32, P, P, I64, P]),
         "sspcg_block_update_gram": (ctypes.c_int, [I64, I32, I32, P, P, P, P, P, P, I64, P, P,
                                                    P, SZ, P]),
         "sspcg_gram_rect": (ctypes.c_int, [I64, I32, I32, P, P, I64, P, P, SZ, P]),

@@ -13,6 +13,7 @@
 #include <array>
 #include <cmath>
 #include <cstddef>
+#include <cstdlib>
 #include <cstring>
 #include <exception>
 #include <functional>
@@ -31,6 +32,15 @@ int hip_fail(hipError_t e, const char* what)
 {
     g_error = std::string(what) + ": " + hipGetErrorString(e);
     return SSPCG_ERR_HIP;
+}
+
+bool debug_sync()
+{
+    static const bool on = [] {
+        const char* v = std::getenv("SSPCG_DEBUG_SYNC");
+        return v && v[0] == '1';
+    }();
+    return on;
 }
 
 }  // namespace sspcg
@@ -138,6 +148,8 @@ int check_params(const sspcg_matrix* A, const sspcg_params* p, bool pcg)
         return arg_error("need 0 <= lambda_min < lambda_max");
     if (p->gram != SSPCG_GRAM_FGS && p->gram != SSPCG_GRAM_CHOLESKY)
         return arg_error("unknown gram solver");
+    if (p->basis != SSPCG_BASIS_CHEBYSHEV && p->basis != SSPCG_BASIS_MONOMIAL)
+        return arg_error("unknown basis");
     if (p->precision != SSPCG_FP64 && p->precision != SSPCG_MIXED)
         return arg_error("unknown precision");
     if (p->precision == SSPCG_MIXED) {
@@ -288,9 +300,13 @@ class PhaseTimer {
     double start_[3] = {0, 0, 0};
 };
 
+// Algorithm 2 after z_1: s SpMV launches; each but the last forms the next
+// basis vector in its epilogue.  Chebyshev: z_2 = alpha dinv.*p_2 - sigma z_1,
+// z_{q+1} = 2 alpha dinv.*p_{q+1} - 2 sigma z_q - gamma z_{q-1}; monomial:
+// z_{q+1} = dinv.*p_{q+1}.
 template <typename T>
-int enqueue_mpk(const sspcg_matrix* A, int s, double al, double sg, T* Z, T* AZ, int64_t ld,
-                const Ctrl* ctrl, hipStream_t st)
+int enqueue_mpk(const sspcg_matrix* A, int s, int basis, double al, double sg, T* Z, T* AZ,
+                int64_t ld, const Ctrl* ctrl, hipStream_t st)
 {
     for (int q = 1; q <= s; ++q) {
         T* zq = Z + (int64_t)(q - 1) * ld;
@@ -298,6 +314,8 @@ int enqueue_mpk(const sspcg_matrix* A, int s, double al, double sg, T* Z, T* AZ,
         int rc;
         if (q == s)
             rc = launch_spmv<T>(A, 0, zq, y, nullptr, nullptr, 0.0, 0.0, 0.0, ctrl, st);
+        else if (basis == SSPCG_BASIS_MONOMIAL)
+            rc = launch_spmv<T>(A, 1, zq, y, nullptr, Z + (int64_t)q * ld, 1.0, 0.0, 0.0, ctrl, st);
         else if (q == 1)
             rc = launch_spmv<T>(A, 1, zq, y, nullptr, Z + (int64_t)q * ld, al, sg, 0.0, ctrl, st);
         else
@@ -333,7 +351,7 @@ int run_sspcg(const sspcg_matrix* A, const sspcg_params* p, const Workspace& w, 
     if (rc != SSPCG_OK) return rc;
     int G = 0;
     tm.start_mark(0, st);
-    rc = enqueue_mpk<T>(A, s, al, sg, Z, AZ, ld, ctrl, st);
+    rc = enqueue_mpk<T>(A, s, p->basis, al, sg, Z, AZ, ld, ctrl, st);
     tm.start_mark(1, st);
     if (rc == SSPCG_OK)
         rc = launch_update_gram<T>(n, s, Z, Q, AZ, AQ, nullptr, r, ld, part, &G, ctrl, st);
@@ -350,7 +368,7 @@ int run_sspcg(const sspcg_matrix* A, const sspcg_params* p, const Workspace& w, 
         tm.mark(k, 1, st);
         if (e == SSPCG_OK) e = launch_norm_step(part, g, k, ctrl, dhist, st);
         tm.mark(k, 2, st);
-        if (e == SSPCG_OK) e = enqueue_mpk<T>(A, s, al, sg, Z, AZ, ld, ctrl, st);
+        if (e == SSPCG_OK) e = enqueue_mpk<T>(A, s, p->basis, al, sg, Z, AZ, ld, ctrl, st);
         tm.mark(k, 3, st);
         if (e == SSPCG_OK) e = launch_gram_rect<T>(n, s, Q, AZ, ld, part, &g, ctrl, st);
         tm.mark(k, 4, st);
@@ -687,6 +705,7 @@ void sspcg_default_params(sspcg_params* p)
     p->check_every = 8;
     p->profile = 0;
     p->sweep_tol = 0.0;
+    p->basis = SSPCG_BASIS_CHEBYSHEV;
 }
 
 int sspcg_matrix_create(int32_t n, int32_t nnz, const int32_t* row_ptr, const int32_t* col,
@@ -930,7 +949,7 @@ int sspcg_spmv(const sspcg_matrix* A, int32_t dtype, const void* x, void* y, ssp
 }
 
 int sspcg_mpk(const sspcg_matrix* A, int32_t dtype, const void* r, int32_t s, double lmin,
-              double lmax, void* Z, void* P, int64_t ld, sspcg_stream stream)
+              double lmax, int32_t basis, void* Z, void* P, int64_t ld, sspcg_stream stream)
 {
     API_TRY
     RETURN_IF(check_matrix(A));
@@ -941,18 +960,19 @@ int sspcg_mpk(const sspcg_matrix* A, int32_t dtype, const void* r, int32_t s, do
     if (s < 1 || s > SSPCG_MAX_S) return arg_error("s must be in 1..16");
     if (ld < A->n) return arg_error("ld < n");
     if (!(lmin >= 0.0) || !(lmax > lmin)) return arg_error("need 0 <= lmin < lmax");
+    if (basis != SSPCG_BASIS_CHEBYSHEV && basis != SSPCG_BASIS_MONOMIAL) return arg_error("unknown basis");
     const double al = 2.0 / (lmax - lmin), sg = (lmax + lmin) / (lmax - lmin);
     hipStream_t st = as_stream(stream);
     if (dtype == SSPCG_F32) {
         float* z = static_cast<float*>(Z);
         float* pp = static_cast<float*>(P);
         RETURN_IF(launch_mpk_start<float>(A->n, static_cast<const float*>(r), A->dinv32, z, pp, st));
-        return enqueue_mpk<float>(A, s, al, sg, z, pp + ld, ld, nullptr, st);
+        return enqueue_mpk<float>(A, s, basis, al, sg, z, pp + ld, ld, nullptr, st);
     }
     double* z = static_cast<double*>(Z);
     double* pp = static_cast<double*>(P);
     RETURN_IF(launch_mpk_start<double>(A->n, static_cast<const double*>(r), A->dinv, z, pp, st));
-    return enqueue_mpk<double>(A, s, al, sg, z, pp + ld, ld, nullptr, st);
+    return enqueue_mpk<double>(A, s, basis, al, sg, z, pp + ld, ld, nullptr, st);
     API_CATCH
 }
 

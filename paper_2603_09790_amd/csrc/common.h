@@ -92,9 +92,14 @@ int hip_fail(hipError_t e, const char* what);
         hipError_t e_ = (call);                                \
         if (e_ != hipSuccess) return ::sspcg::hip_fail(e_, #call); \
     } while (0)
+// SSPCG_DEBUG_SYNC=1 in the environment: synchronize and check after every
+// launch, so an asynchronous failure is reported by the launch that caused it.
+bool debug_sync();
 #define SSPCG_LAUNCHED(what)                                   \
     do {                                                       \
         hipError_t e_ = hipGetLastError();                     \
+        if (e_ == hipSuccess && ::sspcg::debug_sync())         \
+            e_ = hipDeviceSynchronize();                       \
         if (e_ != hipSuccess) return ::sspcg::hip_fail(e_, what); \
     } while (0)
 

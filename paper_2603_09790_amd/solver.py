@@ -117,7 +117,7 @@ class Matrix:
 
 
 def _params(s, sweeps, interval, tol, precision, gram, max_outer, inner_tol, max_refine,
-            check_every, profile=False, sweep_tol=0.0) -> L.Params:
+            check_every, profile=False, sweep_tol=0.0, basis="chebyshev") -> L.Params:
     p = L.Params()
     L.lib().sspcg_default_params(ctypes.byref(p))
     p.s = int(s)
@@ -132,6 +132,7 @@ def _params(s, sweeps, interval, tol, precision, gram, max_outer, inner_tol, max
     p.check_every = int(check_every)
     p.profile = 1 if profile else 0
     p.sweep_tol = float(sweep_tol)
+    p.basis = L.BASIS[basis]
     return p
 
 
@@ -144,8 +145,8 @@ def solve(A: Matrix, b: torch.Tensor, x0: torch.Tensor | None = None, *, s: int 
           sweeps: int = 2, interval=(0.0, 2.0), tol: float = 1e-8, precision: str = "fp64",
           gram: str = "fgs", max_outer: int = 20000, inner_tol: float = 1e-4,
           max_refine: int = 20, check_every: int = 8, history: bool = False,
-          profile: bool = False, sweep_tol: float = 0.0, out: torch.Tensor | None = None,
-          raise_on_error: bool = True):
+          profile: bool = False, sweep_tol: float = 0.0, basis: str = "chebyshev",
+          out: torch.Tensor | None = None, raise_on_error: bool = True):
     """s-step PCG (Algorithm 1) on A x = b.  Returns (x, info).
 
     info['history'] (when history=True): per outer iteration
@@ -154,7 +155,7 @@ def solve(A: Matrix, b: torch.Tensor, x0: torch.Tensor | None = None, *, s: int 
     launches per phase, from HIP events around every phase.
     """
     p = _params(s, sweeps, interval, tol, precision, gram, max_outer, inner_tol, max_refine,
-                check_every, profile, sweep_tol)
+                check_every, profile, sweep_tol, basis)
     dev = A.device
     b = _on(b, dev, torch.float64)
     if out is None:
@@ -235,14 +236,16 @@ def spmv(A: Matrix, x: torch.Tensor) -> torch.Tensor:
     return y
 
 
-def mpk(A: Matrix, r: torch.Tensor, s: int, interval, ld: int | None = None):
+def mpk(A: Matrix, r: torch.Tensor, s: int, interval, ld: int | None = None,
+        basis: str = "chebyshev"):
     """Algorithm 2: returns Z (s, ld) and P (s+1, ld)."""
     ld = ld or A.n
     Z = torch.zeros((s, ld), dtype=r.dtype, device=A.device)
     P = torch.zeros((s + 1, ld), dtype=r.dtype, device=A.device)
     with torch.cuda.device(A.device):
         L.check(L.lib().sspcg_mpk(A.handle, _dtype_code(r), _p(r), s, float(interval[0]),
-                                  float(interval[1]), _p(Z), _p(P), ld, _stream(A.device)),
+                                  float(interval[1]), L.BASIS[basis], _p(Z), _p(P), ld,
+                                  _stream(A.device)),
                 "sspcg_mpk")
     return Z, P
 

@@ -41,8 +41,8 @@ def test_struct_layouts_match_header():
 #include <stdio.h>
 #include "sspcg.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu\n", sizeof(sspcg_params), offsetof(sspcg_params, inner_tol),
-         offsetof(sspcg_params, check_every), sizeof(sspcg_result),
+  printf("%zu %zu %zu %zu %zu %zu %zu\n", sizeof(sspcg_params), offsetof(sspcg_params, inner_tol),
+         offsetof(sspcg_params, check_every), offsetof(sspcg_params, basis), sizeof(sspcg_result),
          offsetof(sspcg_result, relres), offsetof(sspcg_result, device_ms));
   return 0;
 }
@@ -56,7 +56,7 @@ int main(void) {
         vals = list(map(int, subprocess.run([exe], capture_output=True, text=True,
                                             check=True).stdout.split()))
     assert vals == [ctypes.sizeof(L.Params), L.Params.inner_tol.offset,
-                    L.Params.check_every.offset, ctypes.sizeof(L.Result),
+                    L.Params.check_every.offset, L.Params.basis.offset, ctypes.sizeof(L.Result),
                     L.Result.relres.offset, L.Result.device_ms.offset]
 
 
@@ -107,7 +107,7 @@ def test_host_side_argument_errors():
     assert lib.sspcg_block_update_gram(100, 0, 0, X, X, X, X, None, X, 128, X, X, X, 1 << 30,
                                        None) == L.ERR_ARG
     assert lib.sspcg_spmv(None, 0, X, X, None) == L.ERR_ARG
-    assert lib.sspcg_mpk(None, 0, X, 4, 0.0, 2.0, X, X, 128, None) == L.ERR_ARG
+    assert lib.sspcg_mpk(None, 0, X, 4, 0.0, 2.0, 0, X, X, 128, None) == L.ERR_ARG
     assert lib.sspcg_csr_value_grad(None, X, X, X, None) == L.ERR_ARG
     assert lib.sspcg_diffusion7_assemble(None, X, X, None) == L.ERR_ARG
     assert lib.sspcg_diffusion7_theta_grad(None, X, X, X, None) == L.ERR_ARG

@@ -387,3 +387,14 @@ def test_fgs_sweep_tol_on_oracle_systems(traced, key):
         B, code = P.fgs(gpu(st["W"]), gpu(st["B2"]), 300, sweep_tol=d)
         Br, _ = oracle.fgs(st["W"], st["B2"], 300, sweep_tol=d)
         assert np.abs(host(B) - Br).max() <= 1e-10 * np.abs(Br).max()
+
+
+@pytest.mark.parametrize("s", [2, 6])
+def test_mpk_monomial(sys_, s):
+    A, _, interval, M = sys_
+    dinv = oracle.jacobi_inverse(A)
+    r = np.random.default_rng(41).uniform(-1, 1, A.n)
+    Zr, Pr = oracle.mpk(A, dinv, r, s, interval, basis="monomial")
+    Z, Pm = P.mpk(M, gpu(r), s, interval, basis="monomial")
+    col_close(host(Z), Zr, 1e-12)
+    col_close(host(Pm), Pr, 1e-12)

@@ -293,3 +293,53 @@ def test_adaptive_sweeps(poisson5, sweep_tol):
     assert rel(x, xo) <= 1e-8
     # the reduced systems meet the criterion (or the sweep cap was reached)
     assert np.all(info["history"][:, 1] <= sweep_tol * (1 + 1e-6))
+
+
+def test_warm_restart_from_stopped_solve(poisson7):
+    """The solver's state is x: a solve stopped at its iteration limit and
+    restarted from its x converges to the same solution (a new Krylov basis,
+    so not the same trajectory)."""
+    w = poisson7
+    x1, i1 = run(w, s=4, sweeps=2, tol=1e-10, max_outer=40)
+    assert i1["status"] == P.NOT_CONVERGED and i1["outer_iters"] == 40
+    x2, i2 = P.solve(w["M"], gpu(w["b"]), x0=gpu(x1), s=4, sweeps=2, interval=w["interval"],
+                     tol=1e-10)
+    assert i2["status"] == P.OK
+    xs, _ = oracle.pcg(w["A"], w["b"], tol=1e-13)
+    assert rel(x2.cpu().numpy(), xs) <= 1e-7
+
+
+def test_debug_sync_mode():
+    """SSPCG_DEBUG_SYNC=1 (read once per process) synchronizes after every
+    launch; a solve in a child process with it set gives the same result."""
+    import os
+    import subprocess
+    import sys
+    code = (
+        "import numpy as np, torch, paper_2603_09790_amd as P, sspcg_inputs as si\n"
+        "w = si.workload('poisson5', N=32)\n"
+        "M = P.Matrix.from_csr(w['A'], device='cuda:0')\n"
+        "x, i = P.solve(M, torch.from_numpy(w['b']), s=4, sweeps=2, interval=w['interval'],"
+        " tol=1e-10)\n"
+        "np.save('/tmp/sspcg_debug_sync_x.npy', x.cpu().numpy())\n"
+        "print(i['status'], i['outer_iters'])\n")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    env = dict(os.environ, SSPCG_DEBUG_SYNC="1", PYTHONPATH=root)
+    out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True,
+                         timeout=240, cwd=root)
+    assert out.returncode == 0, out.stderr[-2000:]
+    st, iters = map(int, out.stdout.split()[-2:])
+    w = si.workload("poisson5", N=32)
+    M = P.Matrix.from_csr(w["A"], device=DEV)
+    x, info = P.solve(M, gpu(w["b"]), s=4, sweeps=2, interval=w["interval"], tol=1e-10)
+    assert st == 0 and iters == info["outer_iters"]
+    assert np.array_equal(np.load("/tmp/sspcg_debug_sync_x.npy"), x.cpu().numpy())
+
+
+def test_monomial_basis_solve(poisson7):
+    w = poisson7
+    x, info = run(w, s=4, sweeps=2, basis="monomial", tol=1e-30, max_outer=10)
+    xo, ro = oracle.sspcg(w["A"], w["b"], s=4, sweeps=2, interval=w["interval"], tol=1e-30,
+                          max_outer=10, basis="monomial")
+    assert info["outer_iters"] == ro["iters"] == 10
+    assert rel(x, xo) <= 1e-9

@@ -484,3 +484,25 @@ def test_sspcg_with_tight_sweep_tol_matches_cholesky():
                              sweep_tol=1e-13, history=True)
     assert rc["iters"] == rf["iters"]
     assert np.allclose(hf[:, 0], hc[:, 0], rtol=1e-6)
+
+
+# ------------------------------------------------------------ monomial basis
+def test_monomial_basis_is_matrix_powers_and_worse_conditioned():
+    """basis = monomial: z_j = (M^{-1}A)^{j-1} M^{-1} r (the paper's
+    introduction); its Gram matrix is far worse conditioned than the
+    Chebyshev one (the reason for the Chebyshev basis)."""
+    A = si.stencil("7pt", 8, np.exp(si.theta_field(512)))
+    M = si.to_scipy(A).toarray()
+    dinv = oracle.jacobi_inverse(A)
+    r = np.random.default_rng(40).uniform(-1, 1, A.n)
+    lo, hi = si.lanczos_bounds(A)
+    s = 8
+    Zm, Pm = oracle.mpk(A, dinv, r, s, (lo, hi), basis="monomial")
+    v = dinv * r
+    for j in range(s):
+        assert np.abs(Zm[j] - v).max() <= 1e-12 * np.abs(v).max()
+        v = dinv * (M @ v)
+    Zc, Pc = oracle.mpk(A, dinv, r, s, (lo, hi))
+    Wm, _ = oracle.gram(Zm, Pm[1:], Pm[0])
+    Wc, _ = oracle.gram(Zc, Pc[1:], Pc[0])
+    assert np.linalg.cond(Wm) > 1e3 * np.linalg.cond(Wc)
