@@ -111,7 +111,7 @@ def main() -> int:
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-profile", action="store_true",
                     help="time without the per-phase HIP events")
-    ap.add_argument("--mode", choices=["solve", "kernels", "paper"], default="solve",
+    ap.add_argument("--mode", choices=["solve", "kernels", "paper", "configs"], default="solve",
                     help="kernels: a few launches of each hot kernel on the workload and a "
                          "copy kernel of known size (for rocprofv3 counter passes); paper: the "
                          "paper's Gram-solve experiments on its own workload shape")
@@ -137,6 +137,9 @@ def main() -> int:
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
 
+    if args.mode == "configs":
+        print(json.dumps(other_configs(P, torch, dev, args)), flush=True)
+        return 0
     if args.mode == "paper":
         out = paper_experiments(P, torch, dev, args)
         print(json.dumps(out["summary"]), flush=True)
@@ -277,6 +280,84 @@ def counter_traffic():
         return rec["traffic_bytes_per_launch"]
     except (OSError, KeyError, ValueError):
         return None
+
+
+def other_configs(P, torch, dev, args):
+    """Times the other standard workloads (their parity is in the tests):
+    2D Poisson 64^2 (launch-latency bound), 7-point Poisson 128^3 over s and
+    sweeps, the mixed form to 1e-10 on the 192^3 benchmark system, and the
+    differentiable solve (forward + backward) on 7-point diffusion 96^3."""
+    import sspcg_inputs as si
+    out = {}
+    # 2D Poisson 64^2, s = 4, two sweeps, closed-form interval
+    w = si.workload("poisson5")
+    M = P.Matrix.from_csr(w["A"], device=dev)
+    b = torch.from_numpy(w["b"]).to(dev)
+    res = {}
+    for name, fn in (("sspcg", lambda: P.solve(M, b, s=4, sweeps=2, interval=w["interval"], tol=1e-8)),
+                     ("pcg", lambda: P.pcg(M, b, tol=1e-8))):
+        fn()
+        ts = [fn()[1] for _ in range(3)]
+        res[name] = {"time_ms": float(np.median([t["device_ms"] for t in ts])),
+                     "iters": ts[-1]["outer_iters"]}
+        res[name]["us_per_iter"] = 1e3 * res[name]["time_ms"] / max(res[name]["iters"], 1)
+    out["poisson5_64"] = res
+    log(f"[configs] poisson5 64^2: {res}")
+    # 7-point Poisson 128^3 grid of s and sweeps
+    w = si.workload("poisson7")
+    M = P.Matrix.from_csr(w["A"], device=dev)
+    b = torch.from_numpy(w["b"]).to(dev)
+    grid = {}
+    _, ip = P.pcg(M, b, tol=1e-8)
+    grid["pcg"] = {"time_ms": ip["device_ms"], "iters": ip["outer_iters"]}
+    for s_ in (2, 4, 6, 8):
+        for nu in (1, 2, 3):
+            _, i = P.solve(M, b, s=s_, sweeps=nu, interval=w["interval"], tol=1e-8)
+            grid[f"s{s_}_nu{nu}"] = {"time_ms": i["device_ms"], "outer_iters": i["outer_iters"],
+                                     "status": i["status_name"]}
+    out["poisson7_128"] = {"interval": list(w["interval"]), "runs": grid}
+    log(f"[configs] poisson7 128^3: {grid}")
+    # mixed to 1e-10 on the benchmark system, error against an FP64 solve at 1e-12
+    A, b_np, interval = build_workload(192)
+    M = P.Matrix.from_csr(A, fp32=True, device=dev)
+    b = torch.from_numpy(b_np).to(dev)
+    xr, ir = P.solve(M, b, s=6, sweeps=2, interval=interval, tol=1e-12)
+    xm, im = P.solve(M, b, s=6, sweeps=2, interval=interval, tol=1e-10, precision="mixed")
+    x8, i8 = P.solve(M, b, s=6, sweeps=2, interval=interval, tol=1e-10)
+    nr = torch.linalg.vector_norm(xr).item()
+    out["diffusion27_192_to_1e-10"] = {
+        "mixed": {"time_s": im["device_ms"] / 1e3, "refinements": im["refinements"],
+                  "inner_iters": im["outer_iters"], "relres_true": im["relres"],
+                  "rel_error_vs_fp64_1e-12": torch.linalg.vector_norm(xm - xr).item() / nr},
+        "fp64": {"time_s": i8["device_ms"] / 1e3, "outer_iters": i8["outer_iters"],
+                 "rel_error_vs_fp64_1e-12": torch.linalg.vector_norm(x8 - xr).item() / nr},
+        "speedup": i8["device_ms"] / im["device_ms"]}
+    log(f"[configs] diffusion27 192^3 to 1e-10: {out['diffusion27_192_to_1e-10']}")
+    del M, xr, xm, x8
+    # differentiable solve, 7-point diffusion 96^3
+    w = si.workload("diffusion7")
+    A = w["A"]
+    M = P.Matrix.from_csr(A, device=dev)
+    theta = torch.from_numpy(w["theta"]).to(dev).requires_grad_(True)
+    b = torch.from_numpy(w["b"]).to(dev)
+    xt = torch.from_numpy(w["x_target"]).to(dev)
+    opts = dict(s=4, sweeps=2, interval=w["interval"], tol=1e-8)
+    for rep in range(2):
+        theta.grad = None
+        torch.cuda.synchronize()
+        t0 = time.time()
+        x = P.DiffusionSolve.apply(theta, b, M, opts)
+        loss = 0.5 * torch.sum((x - xt) ** 2)
+        torch.cuda.synchronize()
+        t1 = time.time()
+        loss.backward()
+        torch.cuda.synchronize()
+        t2 = time.time()
+    out["diffusion7_96_grad"] = {"forward_s": t1 - t0, "backward_s": t2 - t1,
+                                 "loss": loss.item(),
+                                 "grad_norm": torch.linalg.vector_norm(theta.grad).item()}
+    log(f"[configs] diffusion7 96^3 gradient: {out['diffusion7_96_grad']}")
+    return out
 
 
 def paper_experiments(P, torch, dev, args):

@@ -343,3 +343,33 @@ def test_monomial_basis_solve(poisson7):
                           max_outer=10, basis="monomial")
     assert info["outer_iters"] == ro["iters"] == 10
     assert rel(x, xo) <= 1e-9
+
+
+def test_diffusion_gradient_32cube_finite_differences_and_oracle():
+    """The differentiable form's check instance: 7-point diffusion on 32^3,
+    theta ~ N(0, 0.5^2), loss 0.5 ||x - x_target||^2.  Gradient against
+    central differences (GPU solves at 1e-13) and the oracle's gradient chain."""
+    N = 32
+    w = si.workload("diffusion7", N=N)
+    A, theta, b, xt = w["A"], w["theta"], w["b"], w["x_target"]
+    interval = w["interval"]
+    M = P.Matrix.from_csr(A, device=DEV)
+    opts = dict(s=4, sweeps=2, interval=interval, tol=1e-13)
+    th = gpu(theta).requires_grad_(True)
+    x = P.DiffusionSolve.apply(th, gpu(b), M, opts)
+    loss = 0.5 * torch.sum((x - gpu(xt)) ** 2)
+    loss.backward()
+    g = th.grad.cpu().numpy()
+    u = si.unit_direction(A.n)
+    h = 1e-4
+
+    def loss_at(t):
+        xx = P.DiffusionSolve.apply(gpu(t), gpu(b), M, opts)
+        return 0.5 * torch.sum((xx - gpu(xt)) ** 2).item()
+
+    fd = (loss_at(theta + h * u) - loss_at(theta - h * u)) / (2 * h)
+    assert abs(fd - g @ u) <= 1e-6 * abs(g @ u)
+    xo, _ = oracle.sspcg(A, b, s=4, sweeps=2, interval=interval, tol=1e-14)
+    lam, _ = oracle.sspcg(A, xo - xt, s=4, sweeps=2, interval=interval, tol=1e-14)
+    go = oracle.diffusion7_theta_grad(A, theta, oracle.csr_value_grad(A, lam, xo))
+    assert rel(g, go) <= 1e-8
