@@ -294,10 +294,14 @@ def other_configs(P, torch, dev, args):
     M = P.Matrix.from_csr(w["A"], device=dev)
     b = torch.from_numpy(w["b"]).to(dev)
     res = {}
+    stream = torch.cuda.Stream()
     for name, fn in (("sspcg", lambda: P.solve(M, b, s=4, sweeps=2, interval=w["interval"], tol=1e-8)),
+                     ("sspcg_graph", lambda: P.solve(M, b, s=4, sweeps=2, interval=w["interval"],
+                                                     tol=1e-8, graph=True, check_every=16)),
                      ("pcg", lambda: P.pcg(M, b, tol=1e-8))):
-        fn()
-        ts = [fn()[1] for _ in range(3)]
+        with torch.cuda.stream(stream):
+            fn()
+            ts = [fn()[1] for _ in range(3)]
         res[name] = {"time_ms": float(np.median([t["device_ms"] for t in ts])),
                      "iters": ts[-1]["outer_iters"]}
         res[name]["us_per_iter"] = 1e3 * res[name]["time_ms"] / max(res[name]["iters"], 1)

@@ -98,7 +98,9 @@ typedef struct {
                                    stops sweeping once ||m - W a|| <= sweep_tol ||m|| (the
                                    accuracy criterion of Sec. 3), after at most `sweeps` */
     int32_t basis;              /* sspcg_basis of the Krylov block */
-    int32_t reserved;
+    int32_t use_graph;          /* 1: capture `check_every` outer iterations into one HIP
+                                   graph and replay it (fewer launches; ignored with profile,
+                                   or on the NULL stream, which cannot be captured) */
 } sspcg_params;
 
 /* Outcome of a solve (host struct filled by the solve calls). */

@@ -36,7 +36,7 @@ class Params(ctypes.Structure):
                 ("max_refine", ctypes.c_int32), ("gram", ctypes.c_int32),
                 ("check_every", ctypes.c_int32), ("profile", ctypes.c_int32),
                 ("sweep_tol", ctypes.c_double), ("basis", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("use_graph", ctypes.c_int32)]
 
 
 class Result(ctypes.Structure):

@@ -304,6 +304,31 @@ class PhaseTimer {
 // basis vector in its epilogue.  Chebyshev: z_2 = alpha dinv.*p_2 - sigma z_1,
 // z_{q+1} = 2 alpha dinv.*p_{q+1} - 2 sigma z_q - gamma z_{q-1}; monomial:
 // z_{q+1} = dinv.*p_{q+1}.
+// Captures `n` calls of step(k) on stream st into a graph.  The iterations
+// take no per-iteration argument (the device control block carries the
+// iteration count), so the graph replays any batch.
+int capture_batch(hipStream_t st, int n, const std::function<int(int64_t)>& step,
+                  hipGraph_t* graph, hipGraphExec_t* exec)
+{
+    SSPCG_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed));
+    int rc = SSPCG_OK;
+    for (int k = 0; k < n && rc == SSPCG_OK; ++k) rc = step(k);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(st, &g);
+    if (rc != SSPCG_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    const hipError_t e2 = hipGraphInstantiate(exec, g, nullptr, nullptr, 0);
+    if (e2 != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return hip_fail(e2, "hipGraphInstantiate");
+    }
+    *graph = g;
+    return SSPCG_OK;
+}
+
 template <typename T>
 int enqueue_mpk(const sspcg_matrix* A, int s, int basis, double al, double sg, T* Z, T* AZ,
                 int64_t ld, const Ctrl* ctrl, hipStream_t st)
@@ -366,7 +391,7 @@ int run_sspcg(const sspcg_matrix* A, const sspcg_params* p, const Workspace& w, 
         tm.mark(k, 0, st);
         int e = launch_xr<T>(n, s, Q, AQ, alpha, ld, x, r, dinv, Z, part, &g, ctrl, st);
         tm.mark(k, 1, st);
-        if (e == SSPCG_OK) e = launch_norm_step(part, g, k, ctrl, dhist, st);
+        if (e == SSPCG_OK) e = launch_norm_step(part, g, ctrl, dhist, st);
         tm.mark(k, 2, st);
         if (e == SSPCG_OK) e = enqueue_mpk<T>(A, s, p->basis, al, sg, Z, AZ, ld, ctrl, st);
         tm.mark(k, 3, st);
@@ -392,6 +417,23 @@ int run_sspcg(const sspcg_matrix* A, const sspcg_params* p, const Workspace& w, 
         }
         tm.collect(k0, k1);
     };
+    if (p->use_graph && !p->profile && st != nullptr) {
+        // one batch of iterations captured once, replayed until done
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        rc = capture_batch(st, p->check_every, step, &graph, &exec);
+        if (rc != SSPCG_OK) return rc;
+        auto replay = [&](int64_t k) -> int {
+            if (k % p->check_every != 0) return SSPCG_OK;   // one launch per batch
+            hipError_t e = hipGraphLaunch(exec, st);
+            return e == hipSuccess ? SSPCG_OK : hip_fail(e, "hipGraphLaunch");
+        };
+        const int64_t batches = (max_iter + p->check_every - 1) / p->check_every;
+        rc = run_polled(ctrl, A->host_ctrl, batches * p->check_every, p->check_every, st, replay);
+        (void)hipGraphExecDestroy(exec);
+        (void)hipGraphDestroy(graph);
+        return rc;
+    }
     rc = run_polled(ctrl, A->host_ctrl, max_iter, p->check_every, st, step, on_batch);
     if (rc == SSPCG_OK) tm.fill(const_cast<sspcg_profile*>(&A->profile), s, A->host_ctrl[0].iter);
     return rc;
@@ -706,6 +748,7 @@ void sspcg_default_params(sspcg_params* p)
     p->profile = 0;
     p->sweep_tol = 0.0;
     p->basis = SSPCG_BASIS_CHEBYSHEV;
+    p->use_graph = 0;
 }
 
 int sspcg_matrix_create(int32_t n, int32_t nnz, const int32_t* row_ptr, const int32_t* col,

@@ -238,13 +238,17 @@ __global__ __launch_bounds__(kWave) void k_fgs_direct(int nrhs, const double* __
     if (threadIdx.x == 0) *status = st;
 }
 
+// The outer iteration k is ctrl->iter (the x updates taken so far), so a
+// sequence of iterations has no per-iteration launch argument and can be
+// replayed from a HIP graph.
 __global__ __launch_bounds__(kWave) void k_norm_step(const double* __restrict__ partials, int G,
-                                                     int64_t k, Ctrl* __restrict__ ctrl,
+                                                     Ctrl* __restrict__ ctrl,
                                                      double* __restrict__ hist)
 {
     if (ctrl->done) return;
     const double rr = wave_finish(partials, 0, G);
     if (threadIdx.x != 0) return;
+    const int64_t k = ctrl->iter;
     const double relres = sqrt(rr) / ctrl->nb;
     ctrl->relres = relres;
     ctrl->iter = (int32_t)(k + 1);
@@ -338,10 +342,9 @@ int launch_fgs_direct(int s, int nrhs, const double* W, const double* B, int swe
     return SSPCG_OK;
 }
 
-int launch_norm_step(const double* partials, int G, int64_t k, Ctrl* ctrl, double* hist,
-                     hipStream_t st)
+int launch_norm_step(const double* partials, int G, Ctrl* ctrl, double* hist, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_norm_step, dim3(1), dim3(kWave), 0, st, partials, G, k, ctrl, hist);
+    hipLaunchKernelGGL(k_norm_step, dim3(1), dim3(kWave), 0, st, partials, G, ctrl, hist);
     SSPCG_LAUNCHED("k_norm_step");
     return SSPCG_OK;
 }

@@ -100,9 +100,8 @@ int launch_fgs_step(int s, int which, const double* partials, int G, double* Wbu
                     hipStream_t st);
 int launch_fgs_direct(int s, int nrhs, const double* W, const double* B, int sweeps, double delta,
                       int solver, double* X, int32_t* status, hipStream_t st);
-// Finishes ||r||^2 for outer iteration k: relres, stop test, history.
-int launch_norm_step(const double* partials, int G, int64_t k, Ctrl* ctrl, double* hist,
-                     hipStream_t st);
+// Finishes ||r||^2 of outer iteration ctrl->iter: relres, stop test, history.
+int launch_norm_step(const double* partials, int G, Ctrl* ctrl, double* hist, hipStream_t st);
 // Finishes K partial sums into out[0..K).
 int launch_finish(const double* partials, int K, int G, double* out, hipStream_t st);
 // Kernel-level Gram output: W (mirrored) and b1, or B2 = -sums.

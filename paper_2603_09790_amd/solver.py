@@ -117,7 +117,8 @@ class Matrix:
 
 
 def _params(s, sweeps, interval, tol, precision, gram, max_outer, inner_tol, max_refine,
-            check_every, profile=False, sweep_tol=0.0, basis="chebyshev") -> L.Params:
+            check_every, profile=False, sweep_tol=0.0, basis="chebyshev",
+            graph=False) -> L.Params:
     p = L.Params()
     L.lib().sspcg_default_params(ctypes.byref(p))
     p.s = int(s)
@@ -133,6 +134,7 @@ def _params(s, sweeps, interval, tol, precision, gram, max_outer, inner_tol, max
     p.profile = 1 if profile else 0
     p.sweep_tol = float(sweep_tol)
     p.basis = L.BASIS[basis]
+    p.use_graph = 1 if graph else 0
     return p
 
 
@@ -146,7 +148,7 @@ def solve(A: Matrix, b: torch.Tensor, x0: torch.Tensor | None = None, *, s: int 
           gram: str = "fgs", max_outer: int = 20000, inner_tol: float = 1e-4,
           max_refine: int = 20, check_every: int = 8, history: bool = False,
           profile: bool = False, sweep_tol: float = 0.0, basis: str = "chebyshev",
-          out: torch.Tensor | None = None, raise_on_error: bool = True):
+          graph: bool = False, out: torch.Tensor | None = None, raise_on_error: bool = True):
     """s-step PCG (Algorithm 1) on A x = b.  Returns (x, info).
 
     info['history'] (when history=True): per outer iteration
@@ -155,7 +157,7 @@ def solve(A: Matrix, b: torch.Tensor, x0: torch.Tensor | None = None, *, s: int 
     launches per phase, from HIP events around every phase.
     """
     p = _params(s, sweeps, interval, tol, precision, gram, max_outer, inner_tol, max_refine,
-                check_every, profile, sweep_tol, basis)
+                check_every, profile, sweep_tol, basis, graph)
     dev = A.device
     b = _on(b, dev, torch.float64)
     if out is None:

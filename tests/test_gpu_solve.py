@@ -373,3 +373,30 @@ def test_diffusion_gradient_32cube_finite_differences_and_oracle():
     lam, _ = oracle.sspcg(A, xo - xt, s=4, sweeps=2, interval=interval, tol=1e-14)
     go = oracle.diffusion7_theta_grad(A, theta, oracle.csr_value_grad(A, lam, xo))
     assert rel(g, go) <= 1e-8
+
+
+@pytest.mark.parametrize("check_every", [1, 8])
+def test_graph_replay_matches_eager(poisson5, check_every):
+    """use_graph: a batch of outer iterations captured once into a HIP graph
+    and replayed.  Several graph solves, with eager solves and syncs between
+    them, each equal the eager result bit for bit (same kernels, same order)."""
+    w = poisson5
+    s_ = torch.cuda.Stream()
+    b = gpu(w["b"])
+    with torch.cuda.stream(s_):
+        xe, ie = P.solve(w["M"], b, s=4, sweeps=2, interval=w["interval"], tol=1e-10,
+                         check_every=check_every)
+        for _ in range(3):
+            xg, ig = P.solve(w["M"], b, s=4, sweeps=2, interval=w["interval"], tol=1e-10,
+                             check_every=check_every, graph=True)
+            torch.cuda.synchronize()
+            xe2, _ = P.solve(w["M"], b, s=4, sweeps=2, interval=w["interval"], tol=1e-10,
+                             check_every=check_every)
+            torch.cuda.synchronize()
+            assert ig["status"] == P.OK and ig["outer_iters"] == ie["outer_iters"]
+            assert torch.equal(xg, xe) and torch.equal(xe2, xe)
+    # the iteration limit is respected in graph mode too
+    with torch.cuda.stream(s_):
+        xl, il = P.solve(w["M"], b, s=4, sweeps=2, interval=w["interval"], tol=1e-10,
+                         max_outer=13, check_every=8, graph=True)
+    assert il["status"] == P.NOT_CONVERGED and il["outer_iters"] == 13
