@@ -247,6 +247,10 @@ def main() -> int:
                                                                      "gram_rect") if p in phases))
         out["hbm_gbs_all_streaming"] = tot_b / (tot_ms / 1e3) / 1e9
         out["profiled_ms_total"] = sum(pr[p]["ms"] for p in L_PHASES)
+    if not args.no_profile:
+        # the same FP64 solve without the per-phase events (their cost)
+        _, iu = P.solve(M, b, s=args.s, sweeps=args.sweeps, interval=interval, tol=args.tol)
+        out["fp64"]["time_s_without_phase_events"] = iu["device_ms"] / 1e3
     # classical PCG comparator on the same system (outside the timed steps)
     _, ip = P.pcg(M, b, tol=args.tol)
     out["pcg"] = {"time_s": ip["device_ms"] / 1e3, "iters": ip["outer_iters"],
