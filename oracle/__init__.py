@@ -301,3 +301,72 @@ def diffusion7_theta_grad(A, theta, gval) -> np.ndarray:
     g = np.empty(A.n)
     lib().or_diffusion7_theta_grad(A.n, _p(A.row_ptr), _p(A.col), _p(theta), _p(gval), _p(g))
     return g
+
+
+def lanczos_bounds(A, v0, m=20):
+    """Basis interval from m steps of the Lanczos process.
+
+    The Chebyshev basis is scaled by an interval holding the spectrum of the
+    Jacobi-preconditioned operator M^{-1}A (Sec. "The s-step PCG method with
+    Chebyshev Krylov basis"); M^{-1}A is similar to C = D^{-1/2} A D^{-1/2},
+    which is symmetric, so the process runs on C.  Three-term recurrence from
+    v_1 = v0/||v0||, no reorthogonalisation:
+        alpha_j = v_j^T C v_j
+        w = C v_j - alpha_j v_j - beta_{j-1} v_{j-1},  beta_j = ||w||
+        v_{j+1} = w / beta_j        (stop early when beta_j = 0)
+    The extreme eigenvalues of the tridiagonal T_k = tridiag(beta, alpha,
+    beta) are returned with no safety margin: (lambda_min, lambda_max, k).
+    At most min(m, n) steps are taken.
+    """
+    n = A.n
+    dh = np.sqrt(jacobi_inverse(A))
+    v = _f64(v0).copy()
+    nv = np.sqrt(dot(v, v))
+    if not (nv > 0.0 and np.isfinite(nv)):
+        raise ValueError("start vector has zero norm or non-finite entries")
+    v /= nv
+    v_prev = np.zeros(n)
+    beta_prev = 0.0
+    alphas, betas = [], []
+    for _ in range(min(m, n)):
+        w = dh * spmv(A, dh * v)
+        a = dot(v, w)
+        w = w - a * v - beta_prev * v_prev
+        alphas.append(a)
+        beta = np.sqrt(dot(w, w))
+        if beta == 0.0:
+            break
+        betas.append(beta)
+        v_prev, v, beta_prev = v, w / beta, beta
+    k = len(alphas)
+    T = np.diag(alphas) + np.diag(betas[:k - 1], 1) + np.diag(betas[:k - 1], -1)
+    ev = np.linalg.eigvalsh(T)
+    return float(ev[0]), float(ev[-1]), k
+
+
+def power_bounds(A, v0, rtol=1e-3, max_iter=50):
+    """lambda_min = 0 and the power method's lambda_max of M^{-1}A, M = diag(A).
+
+    Follows Sec. "The s-step PCG method with Chebyshev Krylov basis": one
+    SpMV and one Jacobi application per step, stopping once successive
+    estimates differ by less than rtol relative to the newer one, or after
+    max_iter steps.  The estimate of step l is ||M^{-1} A v_l|| with
+    ||v_l|| = 1, and v_{l+1} = M^{-1} A v_l / that norm.
+    Returns (0.0, lambda_max, steps, estimates).
+    """
+    dinv = jacobi_inverse(A)
+    v = _f64(v0).copy()
+    nv = np.sqrt(dot(v, v))
+    if not (nv > 0.0 and np.isfinite(nv)):
+        raise ValueError("start vector has zero norm or non-finite entries")
+    v /= nv
+    lam_old, lam, hist = 0.0, 0.0, []
+    for _ in range(max_iter):
+        w = dinv * spmv(A, v)
+        lam = np.sqrt(dot(w, w))
+        hist.append(lam)
+        v = w / lam
+        if abs(lam - lam_old) < rtol * abs(lam):
+            break
+        lam_old = lam
+    return 0.0, float(lam), len(hist), np.array(hist)

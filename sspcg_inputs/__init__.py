@@ -36,7 +36,7 @@ import numpy as np
 __all__ = [
     "CSR", "offsets", "stencil", "stencil_numpy", "poisson5", "poisson7", "hpcg27",
     "coeff_blocks", "theta_field", "rhs_uniform", "rhs_normal",
-    "x_target", "unit_direction", "closed_form_bounds", "lanczos_bounds",
+    "x_target", "unit_direction", "closed_form_bounds", "start_vector", "lanczos_bounds",
     "power_bounds", "nnz_formula", "jacobi_inverse", "to_scipy",
     "workload",
 ]
@@ -273,6 +273,11 @@ def closed_form_bounds(kind: str, N: int) -> tuple:
     raise ValueError(kind)
 
 
+def start_vector(n: int, seed: int = SEED_LANCZOS) -> np.ndarray:
+    """Start vector of the interval estimates: U[-1, 1] entries, unnormalised."""
+    return np.random.default_rng(seed).uniform(-1.0, 1.0, size=n)
+
+
 def lanczos_bounds(A: CSR, m: int = 20, seed: int = SEED_LANCZOS) -> tuple:
     """Extreme Ritz values of m-step Lanczos on D^{-1/2} A D^{-1/2}.
 
@@ -290,8 +295,7 @@ def lanczos_bounds(A: CSR, m: int = 20, seed: int = SEED_LANCZOS) -> tuple:
                             w.ctypes.data)
         return w.copy()
 
-    rng = np.random.default_rng(seed)
-    v = rng.uniform(-1.0, 1.0, size=A.n)
+    v = start_vector(A.n, seed)
     v /= np.linalg.norm(v)
     v_prev = np.zeros_like(v)
     alphas, betas = [], []
@@ -325,7 +329,7 @@ def power_bounds(A: CSR, rtol: float = 1e-3, max_iter: int = 50,
     dinv = jacobi_inverse(A)
     ones = np.ones(A.n)
     Av = np.empty(A.n)
-    v = np.random.default_rng(seed).uniform(-1.0, 1.0, size=A.n)
+    v = start_vector(A.n, seed)
     v /= np.linalg.norm(v)
     lam_old = 0.0
     lam = 0.0

@@ -506,3 +506,86 @@ def test_monomial_basis_is_matrix_powers_and_worse_conditioned():
     Wm, _ = oracle.gram(Zm, Pm[1:], Pm[0])
     Wc, _ = oracle.gram(Zc, Pc[1:], Pc[0])
     assert np.linalg.cond(Wm) > 1e3 * np.linalg.cond(Wc)
+
+
+# ---------------------------------------------------------------- basis interval estimates
+
+
+@pytest.mark.parametrize("kind,N", [("5pt", 10), ("7pt", 5), ("27pt", 4)])
+def test_lanczos_full_run_reaches_closed_form_extremes(kind, N):
+    # After n steps the extreme Ritz values are the extreme eigenvalues of
+    # D^{-1}A (they converge first, loss of orthogonality notwithstanding).
+    A = {"5pt": si.poisson5, "7pt": si.poisson7, "27pt": si.hpcg27}[kind](N)
+    lo, hi, k = oracle.lanczos_bounds(A, si.start_vector(A.n), m=A.n)
+    clo, chi = si.closed_form_bounds(kind, N)
+    assert k == A.n
+    assert abs(lo - clo) <= 1e-12 and abs(hi - chi) <= 1e-12
+
+
+def test_lanczos_variable_coefficient_brackets_and_converges():
+    N = 6
+    A = si.stencil("27pt", N, si.coeff_blocks(N, block=2))
+    d = 1.0 / oracle.jacobi_inverse(A)
+    dense = si.to_scipy(A).toarray()
+    ev = np.linalg.eigvalsh(dense / np.sqrt(np.outer(d, d)))
+    v0 = si.start_vector(A.n)
+    # Ritz values interlace: every m-step estimate lies inside the spectrum
+    prev = (np.inf, -np.inf)
+    for m in (2, 5, 10, 20):
+        lo, hi, k = oracle.lanczos_bounds(A, v0, m)
+        assert k == m
+        assert ev[0] - 1e-12 <= lo and hi <= ev[-1] + 1e-12
+        # and they move outwards as the Krylov space grows
+        assert lo <= prev[0] + 1e-14 and hi >= prev[1] - 1e-14
+        prev = (lo, hi)
+    lo, hi, _ = oracle.lanczos_bounds(A, v0, A.n)
+    assert abs(lo - ev[0]) <= 1e-10 * ev[-1] and abs(hi - ev[-1]) <= 1e-10 * ev[-1]
+
+
+def test_lanczos_stops_on_invariant_start():
+    # D^{-1}A = I when A is diagonal: every start vector spans an invariant
+    # subspace.  With even powers of two on the diagonal and a scaled unit
+    # start vector every product is exact, so the first beta is exactly 0.
+    n = 40
+    d = 4.0 ** np.arange(-5, n - 5)
+    A = CSR(n, np.arange(n + 1, dtype=np.int32), np.arange(n, dtype=np.int32), d, None)
+    v0 = np.zeros(n)
+    v0[7] = 3.0
+    lo, hi, k = oracle.lanczos_bounds(A, v0, 20)
+    assert (lo, hi, k) == (1.0, 1.0, 1)
+    with pytest.raises(ValueError):
+        oracle.lanczos_bounds(A, np.zeros(n), 20)
+
+
+def test_lanczos_agrees_with_input_generator_estimate():
+    # Two independent implementations of the same 20-step estimate.
+    A = si.stencil("27pt", 12, si.coeff_blocks(12, block=4))
+    lo, hi, _ = oracle.lanczos_bounds(A, si.start_vector(A.n), 20)
+    ilo, ihi = si.lanczos_bounds(A)
+    assert abs(lo - ilo) <= 1e-12 * ilo and abs(hi - ihi) <= 1e-12 * ihi
+
+
+def test_power_method_monotone_and_converges_to_closed_form():
+    # For constant coefficients M^{-1}A is symmetric; then the estimates
+    # ||M^{-1}A v_l|| never decrease and stay below lambda_max.
+    N = 10
+    A = si.poisson5(N)
+    chi = si.closed_form_bounds("5pt", N)[1]
+    lo, hi, steps, hist = oracle.power_bounds(A, si.start_vector(A.n), rtol=1e-15, max_iter=5000)
+    assert lo == 0.0 and steps < 5000
+    assert np.all(np.diff(hist) >= -1e-15) and np.all(hist <= chi + 1e-14)
+    assert abs(hi - chi) <= 1e-12
+
+
+def test_power_method_stop_rule():
+    A = si.stencil("27pt", 8, si.coeff_blocks(8, block=4))
+    lo, hi, steps, hist = oracle.power_bounds(A, si.start_vector(A.n), rtol=1e-3, max_iter=50)
+    assert steps == len(hist) and hist[-1] == hi
+    rel = np.abs(np.diff(hist)) / hist[1:]
+    # first step whose change is below rtol; none before it
+    if steps < 50:
+        assert rel[steps - 2] < 1e-3 and np.all(rel[:steps - 2] >= 1e-3)
+    else:
+        assert np.all(rel >= 1e-3)
+    _, hi2, steps2, _ = oracle.power_bounds(A, si.start_vector(A.n), rtol=1e-3, max_iter=3)
+    assert steps2 == min(3, steps) and hi2 == hist[steps2 - 1]
