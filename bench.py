@@ -78,6 +78,11 @@ def build_workload(N: int):
     return A, b, interval
 
 
+def si_start_vector(n: int):
+    import sspcg_inputs as si
+    return si.start_vector(n)
+
+
 def cpu_baseline(A, b, interval, s, sweeps, outer_iters_gpu, sample_outer):
     """The oracle on the host, on a bounded sample of the same solve."""
     import oracle
@@ -155,7 +160,22 @@ def main() -> int:
     log(f"[bench] matrix on device in {time.time() - t0:.1f}s: slots {info_m['slots']} "
         f"(padding {info_m['slots'] / A.nnz - 1:.4f}), {info_m['shared_slices']} of "
         f"{info_m['slices']} slices with shared offsets, {info_m['device_bytes'] / 1e9:.2f} GB")
+    t_create = time.time() - t0
     b = torch.from_numpy(b_np).to(dev)
+    # setup, outside the timed region: the basis interval estimated on the
+    # device from the same start vector as the host estimate the solves use
+    v0 = torch.from_numpy(si_start_vector(A.n)).to(dev)
+    P.interval(M, v0, method="lanczos", steps=20)
+    torch.cuda.synchronize()
+    t0 = time.time()
+    est = P.interval(M, v0, method="lanczos", steps=20)
+    setup = {"matrix_create_s": t_create, "interval_device_ms": 1e3 * (time.time() - t0),
+             "interval_device": list(est["interval"]),
+             "interval_device_vs_host": max(abs(est["interval"][i] - interval[i]) / interval[i]
+                                            for i in (0, 1))}
+    log(f"[bench] device Lanczos interval {est['interval']} in "
+        f"{setup['interval_device_ms']:.1f} ms (relative difference from the host estimate "
+        f"{setup['interval_device_vs_host']:.1e})")
     if args.mode == "kernels":
         print(json.dumps(kernel_pass(P, torch, M, A, b, interval, args, col_frac)), flush=True)
         return 0
@@ -255,6 +275,7 @@ def main() -> int:
     _, ip = P.pcg(M, b, tol=args.tol)
     out["pcg"] = {"time_s": ip["device_ms"] / 1e3, "iters": ip["outer_iters"],
                   "relres": ip["relres"]}
+    out["setup"] = setup
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(A, b_np, interval, s, args.sweeps,
@@ -390,12 +411,21 @@ def paper_experiments(P, torch, dev, args):
         f"({time.time() - t0:.1f}s)")
     M = P.Matrix.from_csr(A, device=dev)
     b = torch.from_numpy(b_np).to(dev)
+    v0 = torch.from_numpy(si.start_vector(A.n)).to(dev)
+    torch.cuda.synchronize()
+    t0 = time.time()
+    pw = P.interval(M, v0, method="power", steps=50, rtol=1e-3)
+    pw_ms = 1e3 * (time.time() - t0)
+    log(f"[paper] device power method: {pw['interval']} after {pw['steps']} steps, "
+        f"{pw_ms:.1f} ms")
     tol = 1e-8
     _, ip = P.pcg(M, b, tol=tol, history=True)
     hp = ip["history"]
     runs, summary = {}, {"workload": f"27-point Poisson (HPCG) {N}^3, b = 1, power-method interval",
                          "n": A.n, "nnz": A.nnz, "interval": list(interval), "tol": tol,
-                         "pcg": {"iters": ip["outer_iters"], "time_s": ip["device_ms"] / 1e3}}
+                         "pcg": {"iters": ip["outer_iters"], "time_s": ip["device_ms"] / 1e3},
+                         "device_power_interval": {"interval": list(pw["interval"]),
+                                                   "steps": pw["steps"], "ms": pw_ms}}
     for s in (4, 6):
         for gram, sweeps in (("fgs", 30), ("fgs", 60), ("cholesky", 1)):
             x, info = P.solve(M, b, s=s, sweeps=sweeps, gram=gram, interval=interval, tol=tol,

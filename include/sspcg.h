@@ -203,6 +203,37 @@ int sspcg_pcg_solve(const sspcg_matrix* A, const double* b, double* x, const ssp
                     void* work, size_t work_bytes, sspcg_stream stream, sspcg_result* res,
                     double* history);
 
+/* ---------------------------------------------------------------- basis interval */
+/* The Chebyshev basis needs an interval [lambda_min, lambda_max] holding the
+ * spectrum of M^{-1}A (Sec. 2, the s-step PCG method with Chebyshev Krylov
+ * basis).  Two device estimates: */
+typedef enum {
+    SSPCG_INTERVAL_LANCZOS = 0, /* extreme Ritz values of `steps` Lanczos steps on
+                                   D^{-1/2} A D^{-1/2} (no reorthogonalisation, no margin) */
+    SSPCG_INTERVAL_POWER = 1    /* lambda_min = 0, lambda_max from the power method on M^{-1}A:
+                                   ||M^{-1}A v|| for unit v, stopping when successive estimates
+                                   differ by less than rtol relative, or after `steps` steps */
+} sspcg_interval_method;
+#define SSPCG_MAX_INTERVAL_STEPS 1000
+
+/* Device bytes of the `work` argument of sspcg_interval. */
+int sspcg_interval_work_bytes(const sspcg_matrix* A, int32_t steps, size_t* bytes);
+
+/* Estimates the basis interval on the device.
+ *   method: sspcg_interval_method; steps: 1..SSPCG_MAX_INTERVAL_STEPS (Lanczos
+ *   takes at most n steps and stops early on an invariant subspace, beta = 0);
+ *   rtol: finite, >= 0 (power method only; the paper uses 1e-3 and 50 steps).
+ *   v0 (device, double[n]): start vector, any non-zero scaling; the caller
+ *   draws it (for instance uniform in [-1, 1]).
+ *   work (device, >= sspcg_interval_work_bytes, 256-byte aligned): scratch.
+ *   lambda_min, lambda_max (host, required); steps_taken (host, optional).
+ * A start vector with zero norm or non-finite entries gives SSPCG_ERR_ARG,
+ * after the device has checked it; a non-finite step SSPCG_ERR_NONFINITE.
+ * Blocks until done. */
+int sspcg_interval(const sspcg_matrix* A, int32_t method, int32_t steps, double rtol,
+                   const double* v0, void* work, size_t work_bytes, sspcg_stream stream,
+                   double* lambda_min, double* lambda_max, int32_t* steps_taken);
+
 /* ---------------------------------------------------------------- kernels */
 /* The kernels the solvers are built from, for step-by-step checking.  All
  * enqueue on `stream` and return at once.  `work` is device scratch of at

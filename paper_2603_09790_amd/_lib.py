@@ -21,7 +21,7 @@ EXPORTS = [
     "sspcg_abi_version", "sspcg_status_string", "sspcg_last_error", "sspcg_default_params",
     "sspcg_matrix_create", "sspcg_matrix_update_values", "sspcg_matrix_destroy",
     "sspcg_matrix_info", "sspcg_workspace_bytes", "sspcg_solve", "sspcg_last_profile",
-    "sspcg_pcg_solve",
+    "sspcg_pcg_solve", "sspcg_interval_work_bytes", "sspcg_interval",
     "sspcg_kernel_work_bytes", "sspcg_spmv", "sspcg_mpk", "sspcg_block_update_gram",
     "sspcg_gram_rect", "sspcg_fgs", "sspcg_xr_update", "sspcg_csr_value_grad",
     "sspcg_diffusion7_assemble", "sspcg_diffusion7_theta_grad",
@@ -73,7 +73,7 @@ def lib() -> ctypes.CDLL:
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with "
-                          "`python -m paper_2603_09790_amd.build` (hipcc, gfx950)")
+                          "`python paper_2603_09790_amd/build.py` (hipcc, gfx950)")
     L = ctypes.CDLL(LIB_PATH)
     P, I32, I64, D, SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
     sig = {
@@ -91,6 +91,9 @@ def lib() -> ctypes.CDLL:
         "sspcg_last_profile": (ctypes.c_int, [P, ctypes.POINTER(Profile)]),
         "sspcg_pcg_solve": (ctypes.c_int, [P, P, P, ctypes.POINTER(Params), P, SZ, P,
                                            ctypes.POINTER(Result), P]),
+        "sspcg_interval_work_bytes": (ctypes.c_int, [P, I32, ctypes.POINTER(SZ)]),
+        "sspcg_interval": (ctypes.c_int, [P, I32, I32, D, P, P, SZ, P, ctypes.POINTER(D),
+                                          ctypes.POINTER(D), ctypes.POINTER(I32)]),
         "sspcg_kernel_work_bytes": (SZ, [I32]),
         "sspcg_spmv": (ctypes.c_int, [P, I32, P, P, P]),
         "sspcg_mpk": (ctypes.c_int, [P, I32, P, I32, D, D, I32, P, P, I64, P]),

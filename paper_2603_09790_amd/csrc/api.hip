@@ -970,6 +970,44 @@ int sspcg_pcg_solve(const sspcg_matrix* A, const double* b, double* x, const ssp
     API_CATCH
 }
 
+int sspcg_interval_work_bytes(const sspcg_matrix* A, int32_t steps, size_t* bytes)
+{
+    API_TRY
+    RETURN_IF(check_matrix(A));
+    if (!bytes) return arg_error("bytes is NULL");
+    if (steps < 1 || steps > SSPCG_MAX_INTERVAL_STEPS)
+        return arg_error("steps must be in 1..SSPCG_MAX_INTERVAL_STEPS");
+    *bytes = interval_work_bytes(A->n, steps);
+    return SSPCG_OK;
+    API_CATCH
+}
+
+int sspcg_interval(const sspcg_matrix* A, int32_t method, int32_t steps, double rtol,
+                   const double* v0, void* work, size_t work_bytes, sspcg_stream stream,
+                   double* lambda_min, double* lambda_max, int32_t* steps_taken)
+{
+    API_TRY
+    RETURN_IF(check_matrix(A));
+    if (method != SSPCG_INTERVAL_LANCZOS && method != SSPCG_INTERVAL_POWER)
+        return arg_error("unknown interval method");
+    if (steps < 1 || steps > SSPCG_MAX_INTERVAL_STEPS)
+        return arg_error("steps must be in 1..SSPCG_MAX_INTERVAL_STEPS");
+    if (!(rtol >= 0.0) || !std::isfinite(rtol)) return arg_error("rtol must be finite and >= 0");
+    RETURN_IF(check_vec(v0, SSPCG_F64, "v0"));
+    if (!lambda_min || !lambda_max) return arg_error("lambda_min / lambda_max is NULL");
+    if (!work || !aligned(work, 256)) return arg_error("work is NULL or not 256-byte aligned");
+    if (work_bytes < interval_work_bytes(A->n, steps)) {
+        set_error("interval workspace too small");
+        return SSPCG_ERR_WORKSPACE;
+    }
+    int taken = 0;
+    const int rc = run_interval(A, method, steps, rtol, v0, work, as_stream(stream), lambda_min,
+                                lambda_max, &taken);
+    if (steps_taken) *steps_taken = taken;
+    return rc;
+    API_CATCH
+}
+
 size_t sspcg_kernel_work_bytes(int32_t s)
 {
     return partial_bytes(std::max(1, std::min<int32_t>(s, SSPCG_MAX_S)));

@@ -108,6 +108,12 @@ int launch_finish(const double* partials, int K, int G, double* out, hipStream_t
 int launch_gram_out(int s, int which, const double* partials, int G, double* W, double* b1,
                     hipStream_t st);
 
+// Basis interval estimates (interval.hip): Lanczos or power method on the
+// device; blocks until the host outputs are written.
+size_t interval_work_bytes(int64_t n, int steps);
+int run_interval(const sspcg_matrix* A, int method, int steps, double rtol, const double* v0,
+                 void* work, hipStream_t st, double* lmin, double* lmax, int* steps_taken);
+
 // Differentiation (diff.hip).
 int launch_value_grad(const sspcg_matrix* A, const double* lambda, const double* x,
                       double* gval, hipStream_t st);

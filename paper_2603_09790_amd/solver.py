@@ -223,6 +223,39 @@ def pcg(A: Matrix, b: torch.Tensor, x0: torch.Tensor | None = None, *, tol: floa
     return x, info
 
 
+INTERVAL_METHODS = {"lanczos": 0, "power": 1}
+
+
+def interval(A: Matrix, v0: torch.Tensor, *, method: str = "lanczos", steps: int | None = None,
+             rtol: float = 1e-3) -> dict:
+    """Basis interval [lambda_min, lambda_max] of M^{-1}A estimated on the device.
+
+    method "lanczos": extreme Ritz values of `steps` (default 20) Lanczos
+    steps on D^{-1/2} A D^{-1/2}; "power": lambda_min = 0 and the power
+    method's lambda_max, stopping at relative change < rtol or after `steps`
+    (default 50) steps.  v0: start vector (n values, any non-zero scaling).
+    Returns {"interval": (lo, hi), "steps": steps taken}.
+    """
+    if method not in INTERVAL_METHODS:
+        raise ValueError(f"method must be one of {sorted(INTERVAL_METHODS)}")
+    if steps is None:
+        steps = 20 if method == "lanczos" else 50
+    dev = A.device
+    v0 = _on(v0, dev, torch.float64)
+    if v0.numel() != A.n:
+        raise ValueError("v0 must have n entries")
+    nbytes = ctypes.c_size_t()
+    L.check(L.lib().sspcg_interval_work_bytes(A.handle, steps, ctypes.byref(nbytes)),
+            "sspcg_interval_work_bytes")
+    work = A.workspace(nbytes.value)
+    lo, hi, taken = ctypes.c_double(), ctypes.c_double(), ctypes.c_int32()
+    with torch.cuda.device(dev):
+        L.check(L.lib().sspcg_interval(A.handle, INTERVAL_METHODS[method], steps, rtol, _p(v0),
+                                       _p(work), work.numel(), _stream(dev), ctypes.byref(lo),
+                                       ctypes.byref(hi), ctypes.byref(taken)), "sspcg_interval")
+    return {"interval": (lo.value, hi.value), "steps": taken.value}
+
+
 # ------------------------------------------------------------------ kernels
 
 def _kwork(s: int, device) -> torch.Tensor:

@@ -109,3 +109,18 @@ def test_full_solve_true_residual(big, precision):
     assert rel <= 1.5e-8
     print(f"{precision}: {info['outer_iters']} iterations, {info['device_ms']:.1f} ms, "
           f"true relative residual {rel:.3e}")
+
+
+def test_device_interval_full(big):
+    """Device Lanczos and power estimates at full size against the oracle's."""
+    A, _, interval, M = big
+    v0 = si.start_vector(A.n)
+    out = P.interval(M, torch.from_numpy(v0).to(DEV), method="lanczos", steps=20)
+    lo, hi, k = oracle.lanczos_bounds(A, v0, 20)
+    assert out["steps"] == k == 20
+    assert abs(out["interval"][0] - lo) <= 1e-9 * lo and abs(out["interval"][1] - hi) <= 1e-9 * hi
+    # the fixture's interval is the same estimate from the input generator
+    assert abs(interval[0] - lo) <= 1e-9 * lo and abs(interval[1] - hi) <= 1e-9 * hi
+    pw = P.interval(M, torch.from_numpy(v0).to(DEV), method="power", steps=50, rtol=1e-3)
+    _, phi, pk, _ = oracle.power_bounds(A, v0, rtol=1e-3, max_iter=50)
+    assert abs(pw["interval"][1] - phi) <= 1e-12 * phi and pw["steps"] == pk

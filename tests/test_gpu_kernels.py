@@ -398,3 +398,79 @@ def test_mpk_monomial(sys_, s):
     Z, Pm = P.mpk(M, gpu(r), s, interval, basis="monomial")
     col_close(host(Z), Zr, 1e-12)
     col_close(host(Pm), Pr, 1e-12)
+
+
+# ---------------------------------------------------------------- basis interval estimates
+# Lanczos: the tridiagonal coefficients follow the oracle's to rounding, and
+# 20 steps amplify those differences only mildly, so the Ritz values agree to
+# 1e-9 relative.  Power method: every step is a normalised SpMV, 1e-12.
+
+
+def test_interval_lanczos_matches_oracle(sys_):
+    A, _, _, M = sys_
+    v0 = si.start_vector(A.n)
+    out = P.interval(M, gpu(v0), method="lanczos", steps=20)
+    lo, hi, k = oracle.lanczos_bounds(A, v0, 20)
+    assert out["steps"] == k == 20
+    glo, ghi = out["interval"]
+    assert abs(glo - lo) <= 1e-9 * abs(lo) and abs(ghi - hi) <= 1e-9 * abs(hi)
+
+
+def test_interval_power_matches_oracle(sys_):
+    A, _, _, M = sys_
+    v0 = si.start_vector(A.n)
+    for rtol, steps in ((1e-3, 50), (0.0, 30)):
+        out = P.interval(M, gpu(v0), method="power", steps=steps, rtol=rtol)
+        lo, hi, k, hist = oracle.power_bounds(A, v0, rtol=rtol, max_iter=steps)
+        assert out["interval"][0] == 0.0
+        rel = np.abs(np.diff(hist)) / hist[1:]
+        # the stop step is an integer decided in FP64; compare it exactly
+        # unless the oracle's decision was within rounding of rtol
+        if np.all(np.abs(rel - rtol) > 1e-9 * max(rtol, 1e-300)):
+            assert out["steps"] == k
+            assert abs(out["interval"][1] - hi) <= 1e-12 * hi
+        else:
+            assert abs(out["steps"] - k) <= 1
+
+
+def test_interval_lanczos_full_run_and_step_cap():
+    # steps > n: capped at n; the extremes are then the closed-form ones
+    N = 8
+    A = si.poisson5(N)
+    M = P.Matrix.from_csr(A, device=DEV)
+    out = P.interval(M, gpu(si.start_vector(A.n)), method="lanczos", steps=100)
+    clo, chi = si.closed_form_bounds("5pt", N)
+    assert out["steps"] == A.n
+    assert abs(out["interval"][0] - clo) <= 1e-12 and abs(out["interval"][1] - chi) <= 1e-12
+
+
+def test_interval_lanczos_invariant_start_stops_after_one_step():
+    n = 40
+    d = 4.0 ** np.arange(-5, n - 5)
+    A = si.CSR(n, np.arange(n + 1, dtype=np.int32), np.arange(n, dtype=np.int32), d, None)
+    M = P.Matrix.from_csr(A, device=DEV)
+    v0 = np.zeros(n)
+    v0[7] = 3.0
+    out = P.interval(M, gpu(v0), method="lanczos", steps=20)
+    assert out == {"interval": (1.0, 1.0), "steps": 1}
+    assert oracle.lanczos_bounds(A, v0, 20) == (1.0, 1.0, 1)
+
+
+def test_interval_rejects_bad_input():
+    A = si.poisson5(16)
+    M = P.Matrix.from_csr(A, device=DEV)
+    with pytest.raises(P.SSPCGError) as e:
+        P.interval(M, torch.zeros(A.n, dtype=torch.float64, device=DEV))
+    assert e.value.status == P.ERR_ARG
+    bad = si.start_vector(A.n)
+    bad[3] = np.nan
+    with pytest.raises(P.SSPCGError) as e:
+        P.interval(M, gpu(bad), method="power")
+    assert e.value.status == P.ERR_ARG
+    for kw in (dict(steps=0), dict(steps=1001), dict(method="power", rtol=-1.0)):
+        with pytest.raises(P.SSPCGError) as e:
+            P.interval(M, gpu(si.start_vector(A.n)), **kw)
+        assert e.value.status == P.ERR_ARG
+    # the matrix still works afterwards
+    out = P.interval(M, gpu(si.start_vector(A.n)), method="lanczos", steps=5)
+    assert out["steps"] == 5

@@ -348,7 +348,14 @@ def test_monomial_basis_solve(poisson7):
 def test_diffusion_gradient_32cube_finite_differences_and_oracle():
     """The differentiable form's check instance: 7-point diffusion on 32^3,
     theta ~ N(0, 0.5^2), loss 0.5 ||x - x_target||^2.  Gradient against
-    central differences (GPU solves at 1e-13) and the oracle's gradient chain."""
+    central differences (GPU solves at 1e-13) and the oracle's gradient chain.
+
+    The loss is ~1.7e4 and the solves carry ~1e-13 relative noise, so the
+    difference quotient uses a direction with O(1) entries per cell, the
+    fourth-order central stencil with h = 2e-3 (truncation ~h^4) and loss
+    differences formed without cancellation: L(a) - L(b) =
+    0.5 (x_a - x_b)^T (x_a + x_b - 2 x_target).  With the oracle's solves this
+    reaches ~1e-8 relative; a unit direction at h = 1e-4 only ~1e-4."""
     N = 32
     w = si.workload("diffusion7", N=N)
     A, theta, b, xt = w["A"], w["theta"], w["b"], w["x_target"]
@@ -360,14 +367,19 @@ def test_diffusion_gradient_32cube_finite_differences_and_oracle():
     loss = 0.5 * torch.sum((x - gpu(xt)) ** 2)
     loss.backward()
     g = th.grad.cpu().numpy()
-    u = si.unit_direction(A.n)
-    h = 1e-4
+    u = si.unit_direction(A.n) * np.sqrt(A.n)
+    h = 2e-3
 
-    def loss_at(t):
-        xx = P.DiffusionSolve.apply(gpu(t), gpu(b), M, opts)
-        return 0.5 * torch.sum((xx - gpu(xt)) ** 2).item()
+    def x_at(t):
+        return P.DiffusionSolve.apply(gpu(t), gpu(b), M, opts).cpu().numpy()
 
-    fd = (loss_at(theta + h * u) - loss_at(theta - h * u)) / (2 * h)
+    def dloss(t1, t2):
+        x1, x2 = x_at(t1), x_at(t2)
+        return 0.5 * (x1 - x2) @ (x1 + x2 - 2 * xt)
+
+    d1 = dloss(theta + h * u, theta - h * u)
+    d2 = dloss(theta + 2 * h * u, theta - 2 * h * u)
+    fd = (8 * d1 - d2) / (12 * h)
     assert abs(fd - g @ u) <= 1e-6 * abs(g @ u)
     xo, _ = oracle.sspcg(A, b, s=4, sweeps=2, interval=interval, tol=1e-14)
     lam, _ = oracle.sspcg(A, xo - xt, s=4, sweeps=2, interval=interval, tol=1e-14)
