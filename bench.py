@@ -34,21 +34,27 @@ def log(msg: str) -> None:
     print(msg, file=sys.stderr, flush=True)
 
 
-def spmv_bytes(n: int, nnz: int, elem: int, col_frac: float) -> float:
-    """Algorithmic bytes of one SpMV: the nonzero values (elem each), the
+def stored_values(n: int, nnz: int, symmetric: bool) -> int:
+    """Matrix values one SpMV has to stream: every nonzero, or with the
+    symmetric half storage the diagonal and one triangle."""
+    return (nnz + n) // 2 if symmetric else nnz
+
+
+def spmv_bytes(n: int, nval: int, elem: int, col_frac: float) -> float:
+    """Algorithmic bytes of one SpMV: the nval matrix values (elem each), the
     column indices of the entries stored with explicit columns (4 bytes,
-    col_frac of the nonzeros; slices with a shared offset list store none),
-    the input vector read once and the output written once (2 n elem).  The
-    zero padding of the sliced layout is not counted."""
-    return elem * nnz + 4 * col_frac * nnz + 2 * n * elem
+    col_frac of them; slices with a shared offset list store none), the input
+    vector read once and the output written once (2 n elem).  The zero
+    padding of the sliced layout is not counted."""
+    return elem * nval + 4 * col_frac * nval + 2 * n * elem
 
 
-def spmv_family_bytes(n: int, nnz: int, s: int, elem: int, col_frac: float = 1.0) -> float:
+def spmv_family_bytes(n: int, nval: int, s: int, elem: int, col_frac: float = 1.0) -> float:
     """Algorithmic bytes of one matrix powers kernel (s SpMV launches): s
     SpMVs plus the epilogues, dinv read and z_{q+1} written for q < s (2 n
     elem) and z_{q-1} read for 2 <= q < s (n elem)."""
     epi = sum((2 if q == 1 else 3) * n * elem for q in range(1, s))
-    return s * spmv_bytes(n, nnz, elem, col_frac) + epi
+    return s * spmv_bytes(n, nval, elem, col_frac) + epi
 
 
 def csr_family_bytes(n: int, nnz: int, s: int, elem: int) -> float:
@@ -157,8 +163,11 @@ def main() -> int:
     M = P.Matrix.from_csr(A, fp32=not args.no_mixed, device=dev)
     info_m = M.info()
     col_frac = 1.0 - info_m["shared_slices"] / info_m["slices"]
+    sym = bool(info_m["symmetric"])
+    nval = stored_values(A.n, A.nnz, sym)
     log(f"[bench] matrix on device in {time.time() - t0:.1f}s: slots {info_m['slots']} "
-        f"(padding {info_m['slots'] / A.nnz - 1:.4f}), {info_m['shared_slices']} of "
+        f"({'one triangle, ' if sym else ''}padding {info_m['slots'] / nval - 1:.4f}), "
+        f"{info_m['shared_slices']} of "
         f"{info_m['slices']} slices with shared offsets, {info_m['device_bytes'] / 1e9:.2f} GB")
     t_create = time.time() - t0
     b = torch.from_numpy(b_np).to(dev)
@@ -177,7 +186,8 @@ def main() -> int:
         f"{setup['interval_device_ms']:.1f} ms (relative difference from the host estimate "
         f"{setup['interval_device_vs_host']:.1e})")
     if args.mode == "kernels":
-        print(json.dumps(kernel_pass(P, torch, M, A, b, interval, args, col_frac)), flush=True)
+        print(json.dumps(kernel_pass(P, torch, M, A, b, interval, args, col_frac, nval)),
+              flush=True)
         return 0
     opts = dict(s=args.s, sweeps=args.sweeps, interval=interval, tol=args.tol,
                 profile=not args.no_profile)
@@ -222,7 +232,8 @@ def main() -> int:
         "config": {"workload": f"27-point variable-coefficient diffusion {args.N}^3, "
                                "log-uniform k in [1e-2,1e2] on 8^3 blocks, b~N(0,1), Jacobi",
                    "n": n, "nnz": nnz, "s": s, "sweeps": args.sweeps, "tol": args.tol,
-                   "interval": list(interval), "layout_slots": info_m["slots"]},
+                   "interval": list(interval), "layout_slots": info_m["slots"],
+                   "symmetric_storage": sym},
         "fp64": {"time_s": fp64_s, "outer_iters": last["outer_iters"], "relres": last["relres"],
                  "status": last["status_name"]},
     }
@@ -236,7 +247,7 @@ def main() -> int:
         pr = last["profile"]
         sp = pr["spmv"]
         mpk_calls = sp["launches"] / s
-        b_mpk = spmv_family_bytes(n, nnz, s, 8, col_frac)
+        b_mpk = spmv_family_bytes(n, nval, s, 8, col_frac)
         achieved = b_mpk * mpk_calls / (sp["ms"] / 1e3) / 1e9
         traffic = counter_traffic() if (args.N == 192 and s == 6) else None
         out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
@@ -446,7 +457,7 @@ def paper_experiments(P, torch, dev, args):
     return {"summary": summary, "runs": runs, "pcg_history": hp.tolist()}
 
 
-def kernel_pass(P, torch, M, A, b, interval, args, col_frac):
+def kernel_pass(P, torch, M, A, b, interval, args, col_frac, nval):
     """Launches each hot kernel `reps` times and a plain copy of known size.
 
     Times each kernel with events on the current stream (the one the library
@@ -481,16 +492,16 @@ def kernel_pass(P, torch, M, A, b, interval, args, col_frac):
         log(f"[kernels] {name}: {ms * 1e3:.1f} us, {out[name]['gbs']:.0f} GB/s")
 
     timed("copy_1GiB", lambda: dst.copy_(src), 2 * COPY_BYTES)
-    timed("spmv_f64", lambda: P.spmv(M, x), spmv_bytes(n, A.nnz, 8, col_frac))
+    timed("spmv_f64", lambda: P.spmv(M, x), spmv_bytes(n, nval, 8, col_frac))
     timed("mpk_f64_s%d" % s, lambda: P.mpk(M, r, s, interval, ld=ld),
-          spmv_family_bytes(n, A.nnz, s, 8, col_frac))
+          spmv_family_bytes(n, nval, s, 8, col_frac))
     timed("gram_update", lambda: P.block_update_gram(n, Zb, Qb, AZb, AQb, beta, r),
           (6 * s + 1) * 8 * n)
     timed("gram_rect", lambda: P.gram_rect(n, Qb, AZb), 2 * s * 8 * n)
     timed("xr", lambda: P.xr_update(M, Qb, AQb, alpha, xr_x, r), (2 * s + 6) * 8 * n)
     if M.fp32:
         x32 = x.float()
-        timed("spmv_f32", lambda: P.spmv(M, x32), spmv_bytes(n, A.nnz, 4, col_frac))
+        timed("spmv_f32", lambda: P.spmv(M, x32), spmv_bytes(n, nval, 4, col_frac))
     return {"mode": "kernels", "n": n, "nnz": A.nnz, "s": s, "reps": reps, "kernels": out}
 
 if __name__ == "__main__":

@@ -77,6 +77,7 @@ typedef enum { SSPCG_F64 = 0, SSPCG_F32 = 1 } sspcg_dtype;
 
 /* Flags of sspcg_matrix_create. */
 #define SSPCG_MATRIX_FP32 1     /* also keep FP32 values (needed by SSPCG_MIXED) */
+#define SSPCG_MATRIX_FULL_STORAGE 2  /* store both triangles even when A is symmetric */
 
 /* Parameters of a solve (the requirements of Algorithm 1 plus the basis
  * interval of Sec. 2).  Use sspcg_default_params() and change fields. */
@@ -152,6 +153,11 @@ void sspcg_default_params(sspcg_params* p);
  * each stored column-major and padded to its longest row), the Jacobi
  * scaling 1/diag(A) and, with SSPCG_MATRIX_FP32, FP32 copies of both; it
  * frees them in sspcg_matrix_destroy.  The call synchronizes `stream`.
+ * A stencil-like matrix (one list of at most 32 column offsets fits every
+ * row) that is symmetric bit for bit is stored as its diagonal and upper
+ * triangle only, which halves the values the SpMV streams; the product is
+ * the same, term by term and in the same order.  SSPCG_MATRIX_FULL_STORAGE
+ * keeps both triangles (for later non-symmetric value updates).
  * Solves use only the library's copy, but sspcg_matrix_update_values,
  * sspcg_csr_value_grad and the diffusion calls read the caller's row_ptr and
  * col again: keep them alive as long as the handle is used with those calls.
@@ -161,15 +167,20 @@ int sspcg_matrix_create(int32_t n, int32_t nnz, const int32_t* row_ptr, const in
                         const double* val, int32_t flags, sspcg_stream stream,
                         sspcg_matrix** out);
 /* Replaces the values (same pattern): val is device double[nnz] in CSR
- * order.  Synchronizes `stream`; SSPCG_ERR_BREAKDOWN as for create. */
+ * order.  Synchronizes `stream`.  The values are checked before anything is
+ * changed: SSPCG_ERR_NONFINITE / SSPCG_ERR_BREAKDOWN as for create, and
+ * SSPCG_ERR_UNSUPPORTED for values that are not symmetric when the matrix
+ * stores one triangle; on an error the matrix keeps its old values. */
 int sspcg_matrix_update_values(sspcg_matrix* A, const double* val, sspcg_stream stream);
 int sspcg_matrix_destroy(sspcg_matrix* A);
 /* Size of the library's copy (host outputs, each may be NULL): n, nnz, the
- * stored slots of the sliced layout (nnz plus zero padding), the number of
+ * stored slots of the sliced layout (nnz plus zero padding; with the
+ * symmetric half storage one triangle and the diagonal), the number of
  * 64-row slices and how many of them use a shared offset list (no column
- * indices), and the device bytes held. */
+ * indices), the device bytes held, and 1 if only one triangle is stored. */
 int sspcg_matrix_info(const sspcg_matrix* A, int64_t* n, int64_t* nnz, int64_t* slots,
-                      int64_t* slices, int64_t* shared_slices, int64_t* device_bytes);
+                      int64_t* slices, int64_t* shared_slices, int64_t* device_bytes,
+                      int64_t* symmetric);
 
 /* ---------------------------------------------------------------- solvers */
 /* Workspace (device bytes) that sspcg_solve / sspcg_pcg_solve need. */

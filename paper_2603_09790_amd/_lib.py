@@ -14,6 +14,7 @@ GRAM_FGS, GRAM_CHOLESKY = 0, 1
 F64, F32 = 0, 1
 BASIS = {"chebyshev": 0, "monomial": 1}
 MATRIX_FP32 = 1
+MATRIX_FULL_STORAGE = 2
 MAX_S = 16
 
 # Every symbol the header declares, in header order.
@@ -84,7 +85,7 @@ def lib() -> ctypes.CDLL:
         "sspcg_matrix_create": (ctypes.c_int, [I32, I32, P, P, P, I32, P, ctypes.POINTER(P)]),
         "sspcg_matrix_update_values": (ctypes.c_int, [P, P, P]),
         "sspcg_matrix_destroy": (ctypes.c_int, [P]),
-        "sspcg_matrix_info": (ctypes.c_int, [P] + [ctypes.POINTER(I64)] * 6),
+        "sspcg_matrix_info": (ctypes.c_int, [P] + [ctypes.POINTER(I64)] * 7),
         "sspcg_workspace_bytes": (ctypes.c_int, [P, ctypes.POINTER(Params), ctypes.POINTER(SZ)]),
         "sspcg_solve": (ctypes.c_int, [P, P, P, ctypes.POINTER(Params), P, SZ, P,
                                        ctypes.POINTER(Result), P]),

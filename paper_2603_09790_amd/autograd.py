@@ -17,7 +17,9 @@ from . import solver as S
 
 class SparseSolve(torch.autograd.Function):
     """x = A(val)^{-1} b.  apply(val, b, A, opts) with A a Matrix whose
-    values are replaced by val; opts are keyword arguments of solver.solve."""
+    values are replaced by val; opts are keyword arguments of solver.solve.
+    A matrix stored as one triangle accepts only symmetric val (create it
+    with full_storage=True to pass others)."""
 
     @staticmethod
     def forward(ctx, val, b, A, opts):

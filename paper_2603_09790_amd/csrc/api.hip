@@ -760,7 +760,7 @@ int sspcg_matrix_create(int32_t n, int32_t nnz, const int32_t* row_ptr, const in
     if (n < 1 || nnz < n) return arg_error("need n >= 1 and nnz >= n (diagonal stored)");
     if (!row_ptr || !col || !val) return arg_error("CSR pointer is NULL");
     if (!aligned(row_ptr, 4) || !aligned(col, 4) || !aligned(val, 8)) return arg_error("CSR array misaligned");
-    if (flags & ~SSPCG_MATRIX_FP32) return arg_error("unknown flag");
+    if (flags & ~(SSPCG_MATRIX_FP32 | SSPCG_MATRIX_FULL_STORAGE)) return arg_error("unknown flag");
     hipStream_t st = as_stream(stream);
     auto* A = new sspcg_matrix();
     A->n = n;
@@ -795,7 +795,8 @@ int sspcg_matrix_create(int32_t n, int32_t nnz, const int32_t* row_ptr, const in
     if (e != hipSuccess) return fail(hip_fail(e, "hipHostMalloc"));
     LayoutPlan plan;
     int32_t* d_union = nullptr;
-    int rc = matrix_inspect(A, val, false, &plan, &d_union, st);
+    int rc = matrix_inspect(A, val, false, &plan, &d_union, st, true,
+                            (flags & SSPCG_MATRIX_FULL_STORAGE) == 0);
     auto fail_union = [&](int r) {
         if (d_union) {
             (void)hipFreeAsync(d_union, st);
@@ -811,12 +812,15 @@ int sspcg_matrix_create(int32_t n, int32_t nnz, const int32_t* row_ptr, const in
         // uniform layout: offsets, masks and vector-grouped values only
         A->uniform = 1;
         A->uw = (int32_t)plan.uoff.size();
-        A->slots = A->nslices * kSlice * A->uw;
+        A->usym = plan.usym ? 1 : 0;
+        const int64_t stored = A->uw - (A->usym ? A->uw / 2 : 0);
+        A->slots = A->nslices * kSlice * stored;
         const int64_t rows = A->nslices * kSlice;
         const size_t b_uoff = 256;
         const size_t b_mask = align_up(sizeof(uint32_t) * (size_t)rows, 256);
-        const size_t b_val = align_up(sizeof(double) * (size_t)rows * ((A->uw + 1) / 2 * 2), 256);
-        const size_t b_val32 = f32 ? align_up(sizeof(float) * (size_t)rows * ((A->uw + 3) / 4 * 4), 256) : 0;
+        const size_t b_val = align_up(sizeof(double) * (size_t)rows * ((stored + 1) / 2 * 2), 256);
+        const int64_t stored32 = A->usym ? stored : (stored + 3) / 4 * 4;   // FP32 half: no grouping
+        const size_t b_val32 = f32 ? align_up(sizeof(float) * (size_t)rows * stored32, 256) : 0;
         e = hipMalloc(&A->mem_vals, b_uoff + b_mask + b_val + b_val32);
         if (e != hipSuccess) return fail_union(hip_fail(e, "hipMalloc(matrix values)"));
         char* mv = static_cast<char*>(A->mem_vals);
@@ -825,6 +829,7 @@ int sspcg_matrix_create(int32_t n, int32_t nnz, const int32_t* row_ptr, const in
         A->sval = reinterpret_cast<double*>(mv + b_uoff + b_mask);
         A->sval32 = f32 ? reinterpret_cast<float*>(mv + b_uoff + b_mask + b_val) : nullptr;
         A->mem_bytes = b_small + b_uoff + b_mask + b_val + b_val32;
+        std::copy(plan.uoff.begin(), plan.uoff.end(), A->uoff_host);
         e = hipMemcpyAsync(A->uoff, plan.uoff.data(), sizeof(int32_t) * plan.uoff.size(),
                            hipMemcpyHostToDevice, st);
         if (e != hipSuccess) return fail_union(hip_fail(e, "offsets"));
@@ -874,6 +879,17 @@ int sspcg_matrix_update_values(sspcg_matrix* A, const double* val, sspcg_stream 
     RETURN_IF(check_matrix(A));
     if (!val || !aligned(val, 8)) return arg_error("val is NULL or misaligned");
     hipStream_t st = as_stream(stream);
+    // check everything before the matrix is touched
+    RETURN_IF(matrix_inspect(A, val, true, nullptr, nullptr, st, false));
+    if (A->usym) {
+        bool sym = false;
+        RETURN_IF(matrix_check_symmetric(A, val, &sym, st));
+        if (!sym) {
+            set_error("new values are not symmetric, but the matrix stores one triangle (it was "
+                      "symmetric when created; SSPCG_MATRIX_FULL_STORAGE keeps both)");
+            return SSPCG_ERR_UNSUPPORTED;
+        }
+    }
     RETURN_IF(matrix_inspect(A, val, true, nullptr, nullptr, st));
     return matrix_fill(A, val, true, st);
     API_CATCH
@@ -892,9 +908,11 @@ int sspcg_matrix_destroy(sspcg_matrix* A)
 }
 
 int sspcg_matrix_info(const sspcg_matrix* A, int64_t* n, int64_t* nnz, int64_t* slots,
-                      int64_t* slices, int64_t* shared_slices, int64_t* device_bytes)
+                      int64_t* slices, int64_t* shared_slices, int64_t* device_bytes,
+                      int64_t* symmetric)
 {
     RETURN_IF(check_matrix(A));
+    if (symmetric) *symmetric = A->usym;
     if (n) *n = A->n;
     if (nnz) *nnz = A->nnz;
     if (slots) *slots = A->slots;

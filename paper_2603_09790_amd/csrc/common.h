@@ -53,15 +53,23 @@ static_assert(sizeof(Ctrl) == 128, "Ctrl layout");
 // Uniform layout (uniform != 0): when the offsets of all slices fit one
 // global sorted list of at most 32 (structured-grid stencils), every row is
 // stored against that list, no per-slice data is needed and a lane's
-// entries are grouped in 16-byte vectors (2 FP64 or 4 FP32 values): entry k
-// of lane l of slice c sits at c*64*uwv + (k/V)*64*V + l*V + k%V, V = 16 /
-// sizeof(T), uwv = the list length rounded up to a multiple of V.
+// entries are grouped in 16-byte vectors (2 FP64 or 4 FP32 values): stored
+// entry t of lane l of slice c sits at c*64*uwv + (t/V)*64*V + l*V + t%V,
+// V = 16 / sizeof(T), uwv = the stored entries per row rounded up to a
+// multiple of V.
+// Symmetric half storage (usym != 0): when A is symmetric, bit for bit, and
+// its list is o_k = -o_{uw-1-k} (uw odd, o_{uw/2} = 0), only the entries
+// k >= h = uw/2 are stored, as t = k - h.  Entry k < h of row i is then
+// entry t = h - k of row i + o_k (zero when that row is below 0), which
+// halves the value stream.  FP64 keeps pairs (V = 2); FP32 stores single
+// values (V = 1), so uwv is the stored count itself.
 template <typename T>
 struct Sell {
     int32_t n;
     int32_t uniform;
     int32_t uw, uwv;            // uniform: offsets in the list, stored entries per row
-    const int32_t* uoff;        // uniform: the global offset list
+    int32_t usym;               // uniform: symmetric half storage
+    int32_t uo[32];             // uniform: the global offset list, in the kernel arguments
     int64_t nslices;
     const int64_t* slice_ptr;   // nslices + 1 slot offsets, multiples of 64
     const int64_t* slice_aux;   // kind and offset of each slice, see above
@@ -74,6 +82,7 @@ struct Sell {
 
 // Longest shared offset list a slice may use (the width of a row mask).
 constexpr int kMaxUnion = 32;
+static_assert(sizeof(Sell<double>::uo) == kMaxUnion * sizeof(int32_t), "offset list size");
 
 // Grid of a persistent row kernel: at most `blocks_per_cu` workgroups per CU
 // and never more than fit at once (`resident`, from the occupancy of the

@@ -16,7 +16,9 @@ struct sspcg_matrix {
     int32_t* soff = nullptr;            // owned (inside `mem_vals`)
     uint32_t* smask = nullptr;          // owned (inside `mem_vals`)
     int32_t uniform = 0, uw = 0;        // uniform layout: global offset list length
+    int32_t usym = 0;                   // uniform layout: symmetric half storage
     int32_t* uoff = nullptr;            // owned (inside `mem_vals`)
+    int32_t uoff_host[32] = {};         // the same list, copied into kernel arguments
     double* sval = nullptr;
     float* sval32 = nullptr;
     double* dinv = nullptr;
@@ -43,9 +45,16 @@ struct LayoutPlan {
     std::vector<int64_t> slice_ptr, slice_aux;
     int64_t slots = 0, ncol = 0, nsoff = 0, nshared = 0;
     std::vector<int32_t> uoff;          // non-empty: use the uniform layout with these offsets
+    bool usym = false;                  // uniform: A is symmetric, store one triangle
 };
+// write_dinv = false checks the values without touching the matrix.  With a
+// plan, allow_sym lets the uniform layout use the symmetric half storage.
 int matrix_inspect(sspcg_matrix* A, const double* val, bool values_only, LayoutPlan* plan,
-                   int32_t** d_union, hipStream_t st);
+                   int32_t** d_union, hipStream_t st, bool write_dinv = true,
+                   bool allow_sym = true);
+// Whether the CSR values val (the matrix's pattern) are symmetric bit for
+// bit: a(i, j) equals a(j, i), an absent entry counting as +0.
+int matrix_check_symmetric(const sspcg_matrix* A, const double* val, bool* sym, hipStream_t st);
 int matrix_pack(sspcg_matrix* A, const int32_t* d_union, hipStream_t st);
 int matrix_fill(sspcg_matrix* A, const double* val, bool values_only, hipStream_t st);
 template <typename T>

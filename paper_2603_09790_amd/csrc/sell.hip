@@ -64,7 +64,7 @@ __global__ __launch_bounds__(kRowBlock) void k_inspect(int32_t n, int32_t nnz, i
             }
             if (!has || !(d > 0.0)) f |= kFlagDiag;
             const double di = (has && d > 0.0) ? 1.0 / d : 0.0;
-            dinv[i] = di;
+            if (dinv) dinv[i] = di;
             if (dinv32) dinv32[i] = (float)di;
         }
         if (f) atomicOr(flags, f);
@@ -195,8 +195,36 @@ __global__ __launch_bounds__(kRowBlock) void k_fill(int32_t n, int64_t nslices,
     }
 }
 
+// Symmetry check, one thread per row of a validated pattern: every stored
+// a(i, j) must equal a(j, i) bit for bit, an absent entry counting as +0.
+__global__ __launch_bounds__(kRowBlock) void k_check_symmetric(int32_t n,
+                                                               const int32_t* __restrict__ rp,
+                                                               const int32_t* __restrict__ col,
+                                                               const double* __restrict__ val,
+                                                               int32_t* __restrict__ flags)
+{
+    const int64_t i = (int64_t)blockIdx.x * kRowBlock + threadIdx.x;
+    if (i >= n) return;
+    bool ok = true;
+    const int32_t b = rp[i + 1];
+    for (int32_t e = rp[i]; e < b; ++e) {
+        const int32_t j = col[e];
+        if (j == (int32_t)i) continue;
+        double w = 0.0;
+        const int32_t fb = rp[j + 1];
+        for (int32_t f = rp[j]; f < fb; ++f)
+            if (col[f] == (int32_t)i) {
+                w = val[f];
+                break;
+            }
+        if (__double_as_longlong(w) != __double_as_longlong(val[e])) ok = false;
+    }
+    if (!ok) atomicOr(flags, 1);
+}
+
 // Uniform layout: one thread per row walks its sorted columns against the
-// global offset list; slot of entry k in FP64 (pairs) and FP32 (quads).
+// global offset list; stored entry t = k - h0 (h0 = 0, or uw/2 for the
+// symmetric half storage) in FP64 (pairs) and FP32 (quads).
 __device__ inline int64_t uslot(int64_t c, int k, int lane, int uwv, int V)
 {
     return c * kSlice * uwv + (int64_t)(k / V) * (kSlice * V) + lane * V + k % V;
@@ -207,7 +235,7 @@ __global__ __launch_bounds__(kRowBlock) void k_fill_uniform(int32_t n, int64_t n
                                                             const int32_t* __restrict__ col,
                                                             const double* __restrict__ val,
                                                             const int32_t* __restrict__ uoff, int uw,
-                                                            int uwv64, int uwv32,
+                                                            int h0, int uwv64, int uwv32, int v32,
                                                             uint32_t* __restrict__ smask,
                                                             double* __restrict__ sval,
                                                             float* __restrict__ sval32,
@@ -233,9 +261,11 @@ __global__ __launch_bounds__(kRowBlock) void k_fill_uniform(int32_t n, int64_t n
             ++p;
         }
     }
-    for (int k = 0; k < uwv64; ++k) sval[uslot(c, k, lane, uwv64, 2)] = k < uw ? v[k] : 0.0;
+    for (int t = 0; t < uwv64; ++t)
+        sval[uslot(c, t, lane, uwv64, 2)] = h0 + t < uw ? v[h0 + t] : 0.0;
     if (sval32)
-        for (int k = 0; k < uwv32; ++k) sval32[uslot(c, k, lane, uwv32, 4)] = k < uw ? (float)v[k] : 0.0f;
+        for (int t = 0; t < uwv32; ++t)
+            sval32[uslot(c, t, lane, uwv32, v32)] = h0 + t < uw ? (float)v[h0 + t] : 0.0f;
     if (!values_only) smask[i] = mask;
 }
 
@@ -336,9 +366,71 @@ __device__ inline double row_uniform(const Sell<T>& A, int64_t c, int lane,
 #pragma unroll
         for (int h = 0; h < V; ++h) {
             const int k = j * V + h;
-            const int32_t idx = (m >> k) & 1u ? (int32_t)row + A.uoff[k] : self;
+            const int32_t idx = (m >> k) & 1u ? (int32_t)row + A.uo[k] : self;
             acc = fma((double)v[h], (double)x[idx], acc);
         }
+    }
+    return acc;
+}
+
+// Values per lane vector of the symmetric half storage: FP64 pairs, FP32
+// single values (the reads for negative offsets come from other rows, one
+// value per lane; with FP32 quads they would touch four times the cache
+// lines).
+template <typename T>
+struct HalfV {
+    static constexpr int value = sizeof(T) == 8 ? 2 : 1;
+};
+
+// Row of the symmetric half storage.  Entries k < H (negative offsets) are
+// read from row r = row + o_k, stored entry H - k (an exact zero when r < 0;
+// rows past the boundary otherwise hold the stored zero of the missing pair),
+// entries k >= H from the row's own NV vectors; the sum runs in list order
+// like the full layout's.  These loads are cached: the value a row reads for
+// a negative offset was streamed by row r shortly before.  H, NV > 0: known
+// at compile time; 0: from the matrix.
+template <typename T, int H, int NV>
+__device__ inline double row_uniform_half(const Sell<T>& A, int64_t c, int lane,
+                                          const T* __restrict__ x)
+{
+    constexpr int V = HalfV<T>::value;
+    typedef T VT __attribute__((ext_vector_type(V)));
+    const int64_t row = c * kSlice + lane;
+    const int32_t self = (int32_t)(row < A.n ? row : A.n - 1);
+    const uint32_t m = A.smask[row];
+    const int h = H > 0 ? H : A.uw / 2;
+    const int uw = H > 0 ? 2 * H + 1 : A.uw;
+    const int nv = NV > 0 ? NV : A.uwv / V;
+    const int64_t sw = NV > 0 ? (int64_t)kSlice * NV * V : (int64_t)kSlice * A.uwv;
+    double acc = 0.0;
+    auto lower = [&](int k) {
+        const int64_t r = row + A.uo[k];
+        const int64_t rc = r < 0 ? 0 : r;
+        const int t = h - k;
+        const T v = A.val[(rc >> 6) * sw + (int64_t)(t / V) * (kSlice * V) + (rc & 63) * V + t % V];
+        const int32_t idx = (m >> k) & 1u ? (int32_t)row + A.uo[k] : self;
+        acc = fma(r < 0 ? 0.0 : (double)v, (double)x[idx], acc);
+    };
+    const VT* vp = reinterpret_cast<const VT*>(A.val + c * sw) + lane;
+    auto upper = [&](int j) {
+        const VT v = vp[(int64_t)j * kSlice];
+#pragma unroll
+        for (int e = 0; e < V; ++e) {
+            const int k = h + j * V + e;
+            if (k < uw) {
+                const int32_t idx = (m >> k) & 1u ? (int32_t)row + A.uo[k] : self;
+                acc = fma((double)v[e], (double)x[idx], acc);
+            }
+        }
+    };
+    if constexpr (H > 0) {
+#pragma unroll
+        for (int k = 0; k < H; ++k) lower(k);
+#pragma unroll
+        for (int j = 0; j < NV; ++j) upper(j);
+    } else {
+        for (int k = 0; k < h; ++k) lower(k);
+        for (int j = 0; j < nv; ++j) upper(j);
     }
     return acc;
 }
@@ -347,6 +439,24 @@ template <typename T>
 __device__ inline double uniform_row(const Sell<T>& A, int64_t c, int lane, const T* __restrict__ x)
 {
     constexpr int V = 16 / sizeof(T);
+    if (A.usym) {
+        // (list length, stored vectors per row) of the 27-, 7- and 5-point stencils
+        if constexpr (sizeof(T) == 8) {
+            switch (A.uw * 32 + A.uwv / 2) {
+            case 27 * 32 + 7: return row_uniform_half<T, 13, 7>(A, c, lane, x);
+            case 7 * 32 + 2: return row_uniform_half<T, 3, 2>(A, c, lane, x);
+            case 5 * 32 + 2: return row_uniform_half<T, 2, 2>(A, c, lane, x);
+            default: return row_uniform_half<T, 0, 0>(A, c, lane, x);
+            }
+        } else {
+            switch (A.uw * 32 + A.uwv) {
+            case 27 * 32 + 14: return row_uniform_half<T, 13, 14>(A, c, lane, x);
+            case 7 * 32 + 4: return row_uniform_half<T, 3, 4>(A, c, lane, x);
+            case 5 * 32 + 3: return row_uniform_half<T, 2, 3>(A, c, lane, x);
+            default: return row_uniform_half<T, 0, 0>(A, c, lane, x);
+            }
+        }
+    }
     switch (A.uwv / V) {
     case 2: return row_uniform<T, 2>(A, c, lane, x);     // 5-point (FP32)
     case 3: return row_uniform<T, 3>(A, c, lane, x);     // 5-point (FP64)
@@ -604,18 +714,42 @@ int persistent_grid(int64_t ntiles, int blocks_per_cu, int resident)
 template <typename T>
 Sell<T> sell_view(const sspcg_matrix* A);
 
+// Stored entries per row of the uniform layout (one triangle plus the
+// diagonal with the symmetric half storage).
+static int uniform_stored(const sspcg_matrix* A) { return A->uw - (A->usym ? A->uw / 2 : 0); }
+
+template <typename T>
+static Sell<T> make_view(const sspcg_matrix* A, int uwv, const T* val, const T* dinv)
+{
+    Sell<T> S;
+    S.n = A->n;
+    S.uniform = A->uniform;
+    S.uw = A->uw;
+    S.uwv = uwv;
+    S.usym = A->usym;
+    std::copy(A->uoff_host, A->uoff_host + kMaxUnion, S.uo);
+    S.nslices = A->nslices;
+    S.slice_ptr = A->slice_ptr;
+    S.slice_aux = A->slice_aux;
+    S.col = A->scol;
+    S.soff = A->soff;
+    S.smask = A->smask;
+    S.val = val;
+    S.dinv = dinv;
+    return S;
+}
+
 template <>
 Sell<double> sell_view<double>(const sspcg_matrix* A)
 {
-    return {A->n, A->uniform, A->uw, (A->uw + 1) / 2 * 2, A->uoff, A->nslices, A->slice_ptr,
-            A->slice_aux, A->scol, A->soff, A->smask, A->sval, A->dinv};
+    return make_view<double>(A, (uniform_stored(A) + 1) / 2 * 2, A->sval, A->dinv);
 }
 
 template <>
 Sell<float> sell_view<float>(const sspcg_matrix* A)
 {
-    return {A->n, A->uniform, A->uw, (A->uw + 3) / 4 * 4, A->uoff, A->nslices, A->slice_ptr,
-            A->slice_aux, A->scol, A->soff, A->smask, A->sval32, A->dinv32};
+    const int stored = uniform_stored(A);
+    return make_view<float>(A, A->usym ? stored : (stored + 3) / 4 * 4, A->sval32, A->dinv32);
 }
 
 static int64_t spmv_tiles(const sspcg_matrix* A)
@@ -632,8 +766,22 @@ static int spmv_reduce_grid(const sspcg_matrix* A, K kernel)
     return persistent_grid(spmv_tiles(A), 8, resident);
 }
 
+int matrix_check_symmetric(const sspcg_matrix* A, const double* val, bool* sym, hipStream_t st)
+{
+    const int blocks = (int)((A->n + kRowBlock - 1) / kRowBlock);
+    SSPCG_HIP(hipMemsetAsync(A->dflags, 0, sizeof(int32_t), st));
+    hipLaunchKernelGGL(k_check_symmetric, dim3(blocks), dim3(kRowBlock), 0, st, A->n, A->row_ptr,
+                       A->col, val, A->dflags);
+    SSPCG_LAUNCHED("k_check_symmetric");
+    int32_t h = 1;
+    SSPCG_HIP(hipMemcpyAsync(&h, A->dflags, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    SSPCG_HIP(hipStreamSynchronize(st));
+    *sym = h == 0;
+    return SSPCG_OK;
+}
+
 int matrix_inspect(sspcg_matrix* A, const double* val, bool values_only, LayoutPlan* plan,
-                   int32_t** d_union, hipStream_t st)
+                   int32_t** d_union, hipStream_t st, bool write_dinv, bool allow_sym)
 {
     const int64_t nrows_padded = A->nslices * kSlice;
     const int blocks = (int)((nrows_padded + kRowBlock - 1) / kRowBlock);
@@ -643,7 +791,8 @@ int matrix_inspect(sspcg_matrix* A, const double* val, bool values_only, LayoutP
     SSPCG_HIP(hipMallocAsync((void**)&dwidth, sizeof(int32_t) * A->nslices, st));
     SSPCG_HIP(hipMemsetAsync(A->dflags, 0, sizeof(int32_t), st));
     hipLaunchKernelGGL(k_inspect, dim3(blocks), dim3(kRowBlock), 0, st, A->n, A->nnz, A->nslices,
-                       A->row_ptr, A->col, val, A->dflags, dwidth, A->dinv, A->dinv32, values_only);
+                       A->row_ptr, A->col, val, A->dflags, dwidth, write_dinv ? A->dinv : nullptr,
+                       write_dinv ? A->dinv32 : nullptr, values_only);
     SSPCG_LAUNCHED("k_inspect");
     int32_t hflags = 0;
     SSPCG_HIP(hipMemcpyAsync(&hflags, A->dflags, sizeof(int32_t), hipMemcpyDeviceToHost, st));
@@ -695,8 +844,11 @@ int matrix_inspect(sspcg_matrix* A, const double* val, bool values_only, LayoutP
     }
     plan->slots = plan->slice_ptr[A->nslices];
     // uniform layout: every slice shared, and the union of all their lists
-    // fits one mask and costs at most 2 % more stored entries
+    // fits one mask and costs at most 2 % more stored entries than the
+    // per-slice lists -- or A is symmetric and one triangle of the union
+    // needs fewer entries than the per-slice lists
     plan->uoff.clear();
+    plan->usym = false;
     if (plan->nshared == A->nslices) {
         std::vector<int32_t> hun((size_t)A->nslices * kMaxUnion);
         SSPCG_HIP(hipMemcpy(hun.data(), *d_union, sizeof(int32_t) * hun.size(),
@@ -716,10 +868,21 @@ int matrix_inspect(sspcg_matrix* A, const double* val, bool values_only, LayoutP
                 }
             }
         }
-        if (fits && !all.empty() &&
-            (double)A->nslices * kSlice * all.size() <= 1.02 * (double)plan->slots) {
+        if (fits && !all.empty()) {
             std::sort(all.begin(), all.end());
-            plan->uoff = all;
+            const int uw = (int)all.size();
+            const double rows = (double)A->nslices * kSlice;
+            // symmetric half storage: a list o_k = -o_{uw-1-k} and A = A^T
+            bool mirrored = uw % 2 == 1;
+            for (int k = 0; k < uw && mirrored; ++k) mirrored = all[k] == -all[uw - 1 - k];
+            const int half = (uw - uw / 2 + 1) / 2 * 2;   // stored FP64 entries per row
+            if (allow_sym && mirrored && rows * half <= (double)plan->slots) {
+                bool sym = false;
+                const int rc = matrix_check_symmetric(A, val, &sym, st);
+                if (rc != SSPCG_OK) return rc;
+                plan->usym = sym;
+            }
+            if (plan->usym || rows * uw <= 1.02 * (double)plan->slots) plan->uoff = all;
         }
     }
     return SSPCG_OK;
@@ -739,9 +902,12 @@ int matrix_fill(sspcg_matrix* A, const double* val, bool values_only, hipStream_
     const int64_t nrows_padded = A->nslices * kSlice;
     const int blocks = (int)((nrows_padded + kRowBlock - 1) / kRowBlock);
     if (A->uniform) {
+        const int stored = uniform_stored(A);
         hipLaunchKernelGGL(k_fill_uniform, dim3(blocks), dim3(kRowBlock), 0, st, A->n, A->nslices,
-                           A->row_ptr, A->col, val, A->uoff, A->uw, (A->uw + 1) / 2 * 2,
-                           (A->uw + 3) / 4 * 4, A->smask, A->sval, A->sval32, values_only);
+                           A->row_ptr, A->col, val, A->uoff, A->uw, A->uw - stored,
+                           sell_view<double>(A).uwv, sell_view<float>(A).uwv,
+                           A->usym ? HalfV<float>::value : 4, A->smask, A->sval, A->sval32,
+                           values_only);
         SSPCG_LAUNCHED("k_fill_uniform");
         SSPCG_HIP(hipStreamSynchronize(st));
         return SSPCG_OK;

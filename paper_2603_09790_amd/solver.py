@@ -55,10 +55,13 @@ class Matrix:
 
     row_ptr / col / val may be numpy arrays or tensors; they are copied to the
     device and kept alive for the handle's lifetime.  ``fp32=True`` also keeps
-    FP32 values, which the mixed-precision solve and FP32 kernels need.
+    FP32 values, which the mixed-precision solve and FP32 kernels need.  A
+    symmetric stencil matrix is stored as one triangle unless
+    ``full_storage=True`` (needed to update it later with non-symmetric values).
     """
 
-    def __init__(self, row_ptr, col, val, *, fp32: bool = False, device=None):
+    def __init__(self, row_ptr, col, val, *, fp32: bool = False, full_storage: bool = False,
+                 device=None):
         self.device = _dev(device)
         with torch.cuda.device(self.device):
             self.row_ptr = _on(row_ptr, self.device, torch.int32)
@@ -68,9 +71,10 @@ class Matrix:
             self.nnz = self.col.numel()
             self.fp32 = fp32
             h = ctypes.c_void_p()
+            flags = (L.MATRIX_FP32 if fp32 else 0) | (L.MATRIX_FULL_STORAGE if full_storage else 0)
             st = L.lib().sspcg_matrix_create(self.n, self.nnz, _p(self.row_ptr), _p(self.col),
-                                             _p(self.val), L.MATRIX_FP32 if fp32 else 0,
-                                             _stream(self.device), ctypes.byref(h))
+                                             _p(self.val), flags, _stream(self.device),
+                                             ctypes.byref(h))
             L.check(st, "sspcg_matrix_create")
         self.handle = h
         self._work = None
@@ -92,10 +96,10 @@ class Matrix:
         self.values_tag = tag
 
     def info(self) -> dict:
-        v = [ctypes.c_int64() for _ in range(6)]
+        v = [ctypes.c_int64() for _ in range(7)]
         L.check(L.lib().sspcg_matrix_info(self.handle, *[ctypes.byref(t) for t in v]),
                 "sspcg_matrix_info")
-        keys = ("n", "nnz", "slots", "slices", "shared_slices", "device_bytes")
+        keys = ("n", "nnz", "slots", "slices", "shared_slices", "device_bytes", "symmetric")
         return {k: t.value for k, t in zip(keys, v)}
 
     def workspace(self, nbytes: int) -> torch.Tensor:

@@ -47,8 +47,9 @@ def test_layout_of_full_workload(big):
     info = M.info()
     assert A.nnz == (3 * N - 2) ** 3
     assert info["slices"] == info["shared_slices"] == A.n // 64
-    assert A.nnz <= info["slots"] <= 27 * A.n
-    assert info["slots"] <= 1.02 * A.nnz
+    # symmetric half storage: the diagonal and the 13 upper offsets per row
+    assert info["symmetric"] == 1 and info["slots"] == 14 * A.n
+    assert info["slots"] <= 1.02 * (A.nnz + A.n) / 2
 
 
 def test_spmv_sampled_rows(big):

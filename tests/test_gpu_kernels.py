@@ -53,15 +53,20 @@ def gram_close(got, ref, Q, AQ, tol=1e-12):
 
 
 SYSTEMS = {
-    # name: (kind, N, coefficients)  -- n values include ragged tails (not multiples of 64)
-    "p5_64": ("5pt", 64, None),
-    "d7_13": ("7pt", 13, "theta"),
-    "d27_17": ("27pt", 17, "blocks"),
+    # name: (kind, N, coefficients, storage) -- n values include ragged tails
+    # (not multiples of 64); symmetric matrices are stored as one triangle
+    # unless the storage is "full"
+    "p5_64": ("5pt", 64, None, "auto"),
+    "d7_13": ("7pt", 13, "theta", "auto"),
+    "d27_17": ("27pt", 17, "blocks", "auto"),
+    "p5_64_full": ("5pt", 64, None, "full"),      # uniform layout, both triangles
+    "d7_13_full": ("7pt", 13, "theta", "full"),   # per-slice offset lists
+    "d27_17_full": ("27pt", 17, "blocks", "full"),
 }
 
 
 def system(name):
-    kind, N, coef = SYSTEMS[name]
+    kind, N, coef, _ = SYSTEMS[name]
     n = N * N if kind == "5pt" else N**3
     kap = None
     if coef == "theta":
@@ -77,7 +82,10 @@ def system(name):
 @pytest.fixture(scope="module", params=list(SYSTEMS))
 def sys_(request):
     A, b, interval = system(request.param)
-    return A, b, interval, P.Matrix.from_csr(A, fp32=True, device=DEV)
+    full = SYSTEMS[request.param][3] == "full"
+    M = P.Matrix.from_csr(A, fp32=True, full_storage=full, device=DEV)
+    assert M.info()["symmetric"] == (0 if full else 1)
+    return A, b, interval, M
 
 
 def test_spmv_fp64(sys_):
@@ -102,7 +110,12 @@ def test_matrix_info_and_padding(sys_):
     A, _, _, M = sys_
     info = M.info()
     assert info["n"] == A.n and info["nnz"] == A.nnz
-    assert A.nnz <= info["slots"] <= 1.2 * A.nnz + 64 * 27
+    if info["symmetric"]:
+        # one triangle and the diagonal
+        half = (A.nnz + A.n) // 2
+        assert half <= info["slots"] <= 1.2 * half + 64 * 14
+    else:
+        assert A.nnz <= info["slots"] <= 1.2 * A.nnz + 64 * 27
 
 
 @pytest.mark.parametrize("s", [1, 2, 4, 6, 8, 16])
@@ -370,9 +383,12 @@ def test_stencil_slices_use_shared_offsets():
     # every slice shares one offset list: the 27 stencil offsets inside the
     # grid, fewer on boundary planes (slices hold 64 rows of one x-line half)
     assert info["shared_slices"] == info["slices"] == N**3 // 64
-    assert A.nnz <= info["slots"] <= 27 * N**3
+    # symmetric: the diagonal and the 13 upper offsets of every row
+    assert info["symmetric"] == 1 and info["slots"] == 14 * N**3
     # values only: 8 bytes per slot plus small metadata, no column indices
     assert info["device_bytes"] < 8 * info["slots"] + 40 * A.n
+    Mf = P.Matrix.from_csr(A, full_storage=True, device=DEV)
+    assert Mf.info()["symmetric"] == 0 and A.nnz <= Mf.info()["slots"] <= 27 * N**3
 
 
 @pytest.mark.parametrize("key", KEYS)
@@ -474,3 +490,84 @@ def test_interval_rejects_bad_input():
     # the matrix still works afterwards
     out = P.interval(M, gpu(si.start_vector(A.n)), method="lanczos", steps=5)
     assert out["steps"] == 5
+
+
+
+# ---------------------------------------------------------------- symmetric half storage
+
+
+@pytest.mark.parametrize("kind,N", [("5pt", 40), ("7pt", 13), ("27pt", 17)])
+def test_half_storage_is_the_same_product(kind, N):
+    """One triangle stored: the SpMV sums the same terms in the same order, so
+    FP64 and FP32 products equal the full storage's bit for bit."""
+    n = N * N if kind == "5pt" else N**3
+    kap = np.exp(si.theta_field(n))
+    A = si.stencil(kind, N, kap)
+    Mh = P.Matrix.from_csr(A, fp32=True, device=DEV)
+    Mf = P.Matrix.from_csr(A, fp32=True, full_storage=True, device=DEV)
+    assert Mh.info()["symmetric"] == 1 and Mf.info()["symmetric"] == 0
+    assert Mh.info()["device_bytes"] < 0.7 * Mf.info()["device_bytes"]
+    rng = np.random.default_rng(40)
+    x = gpu(rng.normal(size=A.n))
+    assert torch.equal(P.spmv(Mh, x), P.spmv(Mf, x))
+    x32 = x.float()
+    assert torch.equal(P.spmv(Mh, x32), P.spmv(Mf, x32))
+    interval = si.lanczos_bounds(A)
+    for Z, Pm in zip(P.mpk(Mh, x, 6, interval), P.mpk(Mf, x, 6, interval)):
+        assert torch.equal(Z, Pm)
+
+
+def test_nonsymmetric_stencil_keeps_full_storage():
+    N = 12
+    A = si.stencil("7pt", N, np.exp(si.theta_field(N**3)))
+    val = A.val.copy()
+    val[A.row_ptr[100] + 1] *= 1.0 + 2.0**-40      # one off-diagonal entry, one ulp-ish off
+    B = si.CSR(A.n, A.row_ptr, A.col, val, A.shape3)
+    M = P.Matrix.from_csr(B, fp32=True, device=DEV)
+    assert M.info()["symmetric"] == 0
+    x = np.random.default_rng(41).normal(size=A.n)
+    y = host(P.spmv(M, gpu(x)))
+    ref = oracle.spmv(B, x)
+    assert np.abs(y - ref).max() <= 1e-14 * np.abs(ref).max()
+    x32 = x.astype(np.float32)
+    assert np.array_equal(host(P.spmv(M, gpu(x32))), oracle.spmv_f32(B, B.val.astype(np.float32), x32))
+
+
+def test_update_values_checks_before_changing_anything():
+    N = 12
+    A = si.stencil("7pt", N, np.exp(si.theta_field(N**3)))
+    M = P.Matrix.from_csr(A, device=DEV)
+    assert M.info()["symmetric"] == 1
+    x = gpu(np.random.default_rng(42).normal(size=A.n))
+    interval = si.lanczos_bounds(A)
+    y0 = P.spmv(M, x).clone()
+    Z0, _ = P.mpk(M, x, 3, interval)            # uses 1/diag(A) too
+    # not symmetric: refused on a half-storage matrix, nothing changed
+    bad = A.val.copy()
+    bad[A.row_ptr[50] + 1] *= 1.5
+    with pytest.raises(P.SSPCGError) as e:
+        M.update_values(gpu(bad))
+    assert e.value.status == P.ERR_UNSUPPORTED
+    # non-finite and non-positive diagonal: refused, nothing changed
+    nan = A.val.copy()
+    nan[7] = np.nan
+    with pytest.raises(P.SSPCGError) as e:
+        M.update_values(gpu(nan))
+    assert e.value.status == P.ERR_NONFINITE
+    neg = A.val.copy()
+    diag = [a for i in range(A.n) for a in range(A.row_ptr[i], A.row_ptr[i + 1]) if A.col[a] == i]
+    neg[diag[3]] = -1.0
+    with pytest.raises(P.SSPCGError) as e:
+        M.update_values(gpu(neg))
+    assert e.value.status == P.ERR_BREAKDOWN
+    assert torch.equal(P.spmv(M, x), y0)
+    assert torch.equal(P.mpk(M, x, 3, interval)[0], Z0)
+    # symmetric new values are accepted and used
+    M.update_values(gpu(2.0 * A.val))
+    assert torch.equal(P.spmv(M, x), 2.0 * y0)
+    # full storage accepts non-symmetric values
+    Mf = P.Matrix.from_csr(A, full_storage=True, device=DEV)
+    Mf.update_values(gpu(bad))
+    Bm = si.CSR(A.n, A.row_ptr, A.col, bad, A.shape3)
+    ref = oracle.spmv(Bm, host(x))
+    assert np.abs(host(P.spmv(Mf, x)) - ref).max() <= 1e-14 * np.abs(ref).max()
