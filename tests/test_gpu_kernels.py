@@ -571,3 +571,53 @@ def test_update_values_checks_before_changing_anything():
     Bm = si.CSR(A.n, A.row_ptr, A.col, bad, A.shape3)
     ref = oracle.spmv(Bm, host(x))
     assert np.abs(host(P.spmv(Mf, x)) - ref).max() <= 1e-14 * np.abs(ref).max()
+
+
+def stencil_csr(kind, N):
+    """9-point 2D (list length 9) or 19-point 3D (19) stencils: no
+    compile-time row variant exists for them, so the generic ones run."""
+    import scipy.sparse as sp
+    B = sp.diags([1.0, 1.0, 1.0], [-1, 0, 1], shape=(N, N))
+    if kind == "9pt":
+        K = sp.kron(B, B)                       # centre + 8 neighbours
+        A = 9.5 * sp.eye(N * N) - K
+        shape = (1, N, N)
+    else:
+        # 19 points: the 3x3x3 cube without its 8 corners
+        I = sp.eye(N)
+        T = sp.diags([1.0, 1.0], [-1, 1], shape=(N, N))
+        faces = sp.kron(sp.kron(T, I), I) + sp.kron(sp.kron(I, T), I) + sp.kron(sp.kron(I, I), T)
+        edges = sp.kron(sp.kron(T, T), I) + sp.kron(sp.kron(T, I), T) + sp.kron(sp.kron(I, T), T)
+        A = 19.5 * sp.eye(N**3) - faces - 0.5 * edges
+        shape = (N, N, N)
+    A = A.tocsr()
+    A.sort_indices()
+    rng = np.random.default_rng(44)
+    # symmetric positive scaling keeps A symmetric and varies the values
+    d = rng.uniform(0.5, 2.0, A.shape[0])
+    A = (sp.diags(d) @ A @ sp.diags(d)).tocsr()
+    A.sort_indices()
+    return si.CSR(A.shape[0], A.indptr.astype(np.int32), A.indices.astype(np.int32),
+                  A.data.copy(), shape)
+
+
+@pytest.mark.parametrize("kind,N", [("9pt", 48), ("9pt", 37), ("19pt", 12), ("19pt", 9)])
+@pytest.mark.parametrize("full", [False, True])
+def test_generic_stencil_rows(kind, N, full):
+    A = stencil_csr(kind, N)
+    M = P.Matrix.from_csr(A, fp32=True, full_storage=full, device=DEV)
+    info = M.info()
+    assert info["symmetric"] == (0 if full else 1)
+    x = np.random.default_rng(45).normal(size=A.n)
+    y = host(P.spmv(M, gpu(x)))
+    ref = oracle.spmv(A, x)
+    absA = A.__class__(A.n, A.row_ptr, A.col, np.abs(A.val), A.shape3)
+    assert np.all(np.abs(y - ref) <= 1e-14 * oracle.spmv(absA, np.abs(x)))
+    x32 = x.astype(np.float32)
+    assert np.array_equal(host(P.spmv(M, gpu(x32))), oracle.spmv_f32(A, A.val.astype(np.float32), x32))
+    b = si.rhs_uniform(A.n)
+    interval = si.lanczos_bounds(A)
+    xg, ig = P.solve(M, gpu(b), s=4, sweeps=3, interval=interval, tol=1e-30, max_outer=15)
+    xo, ro = oracle.sspcg(A, b, s=4, sweeps=3, interval=interval, tol=1e-30, max_outer=15)
+    assert ig["outer_iters"] == ro["iters"] == 15
+    assert np.linalg.norm(host(xg) - xo) <= 1e-10 * np.linalg.norm(xo)
