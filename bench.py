@@ -294,6 +294,14 @@ def main() -> int:
         # the same FP64 solve without the per-phase events (their cost)
         _, iu = P.solve(M, b, s=args.s, sweeps=args.sweeps, interval=interval, tol=args.tol)
         out["fp64"]["time_s_without_phase_events"] = iu["device_ms"] / 1e3
+    # and replayed from HIP graphs of check_every outer iterations (fewer launches)
+    with torch.cuda.stream(torch.cuda.Stream(device=dev)):
+        P.solve(M, b, s=args.s, sweeps=args.sweeps, interval=interval, tol=args.tol, graph=True)
+        _, ig = P.solve(M, b, s=args.s, sweeps=args.sweeps, interval=interval, tol=args.tol,
+                        graph=True)
+    torch.cuda.synchronize()
+    out["fp64"]["time_s_graph_replay"] = ig["device_ms"] / 1e3
+    out["fp64"]["outer_iters_graph_replay"] = ig["outer_iters"]
     # classical PCG comparator on the same system (outside the timed steps)
     _, ip = P.pcg(M, b, tol=args.tol)
     out["pcg"] = {"time_s": ip["device_ms"] / 1e3, "iters": ip["outer_iters"],
