@@ -830,6 +830,7 @@ int sspcg_matrix_create(int32_t n, int32_t nnz, const int32_t* row_ptr, const in
         A->sval32 = f32 ? reinterpret_cast<float*>(mv + b_uoff + b_mask + b_val) : nullptr;
         A->mem_bytes = b_small + b_uoff + b_mask + b_val + b_val32;
         std::copy(plan.uoff.begin(), plan.uoff.end(), A->uoff_host);
+        plan_lds(A);
         e = hipMemcpyAsync(A->uoff, plan.uoff.data(), sizeof(int32_t) * plan.uoff.size(),
                            hipMemcpyHostToDevice, st);
         if (e != hipSuccess) return fail_union(hip_fail(e, "offsets"));

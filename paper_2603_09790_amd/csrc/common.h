@@ -70,6 +70,17 @@ struct Sell {
     int32_t uw, uwv;            // uniform: offsets in the list, stored entries per row
     int32_t usym;               // uniform: symmetric half storage
     int32_t uo[32];             // uniform: the global offset list, in the kernel arguments
+    // LDS staging of x (uniform layout): the gathers x[row + o_k] of a
+    // 256-row tile starting at row a fall into one window per run of
+    // consecutive offsets (o, o+1, ...): x[a + lo .. a + lo + w), w = 256 +
+    // the run's span.  Each workgroup copies its windows to LDS slots of
+    // lds_w elements with contiguous loads, then reads entry k of tile row t
+    // at sx[lds_k[k] + t].  lds_n = 0: gathers from memory (more than
+    // kMaxWindows runs, or the layout is not uniform).
+    int32_t lds_n;              // staged elements per tile (ncl * lds_w)
+    int32_t ncl, lds_w;         // runs (windows), LDS slot length (the longest window)
+    int32_t cl_lo[32], cl_w[32];   // first offset and length of each window
+    int32_t lds_k[32];          // LDS index of entry k for tile row 0 (stored pads: any window)
     int64_t nslices;
     const int64_t* slice_ptr;   // nslices + 1 slot offsets, multiples of 64
     const int64_t* slice_aux;   // kind and offset of each slice, see above
@@ -82,6 +93,7 @@ struct Sell {
 
 // Longest shared offset list a slice may use (the width of a row mask).
 constexpr int kMaxUnion = 32;
+constexpr int kMaxWindows = 12;    // LDS windows of x per tile at most (about 27 KB in FP64)
 static_assert(sizeof(Sell<double>::uo) == kMaxUnion * sizeof(int32_t), "offset list size");
 
 // Grid of a persistent row kernel: at most `blocks_per_cu` workgroups per CU
@@ -90,8 +102,9 @@ static_assert(sizeof(Sell<double>::uo) == kMaxUnion * sizeof(int32_t), "offset l
 // multiple of kNumXcd blocks.
 int persistent_grid(int64_t ntiles, int blocks_per_cu, int resident = 1 << 20);
 int num_cus();
-// Workgroups of `kernel` (256 threads) that fit on one CU at once.
-int resident_blocks(const void* kernel, int threads);
+// Workgroups of `kernel` (256 threads, dyn_lds bytes of dynamic LDS) that
+// fit on one CU at once.
+int resident_blocks(const void* kernel, int threads, size_t dyn_lds = 0);
 
 // Error plumbing for the C ABI.
 void set_error(const std::string& msg);

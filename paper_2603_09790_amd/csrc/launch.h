@@ -19,6 +19,8 @@ struct sspcg_matrix {
     int32_t usym = 0;                   // uniform layout: symmetric half storage
     int32_t* uoff = nullptr;            // owned (inside `mem_vals`)
     int32_t uoff_host[32] = {};         // the same list, copied into kernel arguments
+    int32_t lds_n = 0, ncl = 0, lds_w = 0;   // LDS staging of x (see Sell), computed at creation
+    int32_t cl_lo[32] = {}, cl_w[32] = {}, lds_k[32] = {};
     double* sval = nullptr;
     float* sval32 = nullptr;
     double* dinv = nullptr;
@@ -57,6 +59,8 @@ int matrix_inspect(sspcg_matrix* A, const double* val, bool values_only, LayoutP
 int matrix_check_symmetric(const sspcg_matrix* A, const double* val, bool* sym, hipStream_t st);
 int matrix_pack(sspcg_matrix* A, const int32_t* d_union, hipStream_t st);
 int matrix_fill(sspcg_matrix* A, const double* val, bool values_only, hipStream_t st);
+// Windows of the LDS staging of x for the uniform offset list (host only).
+void plan_lds(sspcg_matrix* A);
 template <typename T>
 int launch_mpk_start(int64_t n, const T* r, const T* dinv, T* z1, T* p1, hipStream_t st);
 

@@ -17,6 +17,7 @@
 
 #include <algorithm>
 #include <climits>
+#include <map>
 #include <mutex>
 #include <unordered_map>
 #include <vector>
@@ -467,6 +468,133 @@ __device__ inline double uniform_row(const Sell<T>& A, int64_t c, int lane, cons
     }
 }
 
+// ---- uniform layout with x staged in LDS (Sell::lds_n > 0)
+
+// Copies the tile's windows of x to LDS (all threads of the workgroup; the
+// caller synchronizes).  Thread t loads element t of every window, and the
+// few elements past 256 of each, into registers before it stores any, so
+// all loads are in flight together.  Elements outside [0, n) are staged as
+// 0: the entries that would read them are stored zeros.
+template <typename T>
+__device__ inline void stage_x(const Sell<T>& A, int64_t a, const T* __restrict__ x,
+                               T* __restrict__ sx)
+{
+    const int t = threadIdx.x;
+    T head[kMaxWindows], tail[kMaxWindows];
+#pragma unroll
+    for (int j = 0; j < kMaxWindows; ++j) {
+        head[j] = tail[j] = (T)0;
+        if (j < A.ncl) {
+            const int64_t g = a + A.cl_lo[j] + t;
+            if (g >= 0 && g < A.n) head[j] = x[g];
+            const int64_t g2 = g + kRowBlock;
+            if (kRowBlock + t < A.cl_w[j] && g2 >= 0 && g2 < A.n) tail[j] = x[g2];
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < kMaxWindows; ++j) {
+        if (j < A.ncl) {
+            sx[j * A.lds_w + t] = head[j];
+            if (kRowBlock + t < A.cl_w[j]) sx[j * A.lds_w + kRowBlock + t] = tail[j];
+        }
+    }
+}
+
+// Full storage, x from LDS: entry k of tile row t multiplies sx[lds_k[k] + t]
+// (a row without that neighbour holds a stored zero there, so no mask is
+// needed; the stored padding entries point at a valid element too).
+template <typename T, int NV>
+__device__ inline double row_uniform_lds(const Sell<T>& A, int64_t c, int lane, int t,
+                                         const T* __restrict__ sx)
+{
+    constexpr int V = 16 / sizeof(T);
+    typedef typename Vec16<T>::type VT;
+    const VT* vp = reinterpret_cast<const VT*>(A.val + c * kSlice * A.uwv) + lane;
+    const int nv = NV > 0 ? NV : A.uwv / V;
+    double acc = 0.0;
+#pragma unroll 4
+    for (int j = 0; j < nv; ++j) {
+        const VT v = __builtin_nontemporal_load(vp + (int64_t)j * kSlice);
+#pragma unroll
+        for (int h = 0; h < V; ++h)
+            acc = fma((double)v[h], (double)sx[A.lds_k[j * V + h] + t], acc);
+    }
+    return acc;
+}
+
+// Symmetric half storage, x from LDS (see row_uniform_half).
+template <typename T, int H, int NV>
+__device__ inline double row_uniform_half_lds(const Sell<T>& A, int64_t c, int lane, int t,
+                                              const T* __restrict__ sx)
+{
+    constexpr int V = HalfV<T>::value;
+    typedef T VT __attribute__((ext_vector_type(V)));
+    const int64_t row = c * kSlice + lane;
+    const int h = H > 0 ? H : A.uw / 2;
+    const int uw = H > 0 ? 2 * H + 1 : A.uw;
+    const int nv = NV > 0 ? NV : A.uwv / V;
+    const int64_t sw = NV > 0 ? (int64_t)kSlice * NV * V : (int64_t)kSlice * A.uwv;
+    double acc = 0.0;
+    auto lower = [&](int k) {
+        const int64_t r = row + A.uo[k];
+        const int64_t rc = r < 0 ? 0 : r;
+        const int tt = h - k;
+        const T v = A.val[(rc >> 6) * sw + (int64_t)(tt / V) * (kSlice * V) + (rc & 63) * V + tt % V];
+        acc = fma(r < 0 ? 0.0 : (double)v, (double)sx[A.lds_k[k] + t], acc);
+    };
+    const VT* vp = reinterpret_cast<const VT*>(A.val + c * sw) + lane;
+    auto upper = [&](int j) {
+        const VT v = vp[(int64_t)j * kSlice];
+#pragma unroll
+        for (int e = 0; e < V; ++e) {
+            const int k = h + j * V + e;
+            if (k < uw) acc = fma((double)v[e], (double)sx[A.lds_k[k] + t], acc);
+        }
+    };
+    if constexpr (H > 0) {
+#pragma unroll
+        for (int k = 0; k < H; ++k) lower(k);
+#pragma unroll
+        for (int j = 0; j < NV; ++j) upper(j);
+    } else {
+        for (int k = 0; k < h; ++k) lower(k);
+        for (int j = 0; j < nv; ++j) upper(j);
+    }
+    return acc;
+}
+
+template <typename T>
+__device__ inline double uniform_row_lds(const Sell<T>& A, int64_t c, int lane, int t,
+                                         const T* __restrict__ sx)
+{
+    constexpr int V = 16 / sizeof(T);
+    if (A.usym) {
+        if constexpr (sizeof(T) == 8) {
+            switch (A.uw * 32 + A.uwv / 2) {
+            case 27 * 32 + 7: return row_uniform_half_lds<T, 13, 7>(A, c, lane, t, sx);
+            case 7 * 32 + 2: return row_uniform_half_lds<T, 3, 2>(A, c, lane, t, sx);
+            case 5 * 32 + 2: return row_uniform_half_lds<T, 2, 2>(A, c, lane, t, sx);
+            default: return row_uniform_half_lds<T, 0, 0>(A, c, lane, t, sx);
+            }
+        } else {
+            switch (A.uw * 32 + A.uwv) {
+            case 27 * 32 + 14: return row_uniform_half_lds<T, 13, 14>(A, c, lane, t, sx);
+            case 7 * 32 + 4: return row_uniform_half_lds<T, 3, 4>(A, c, lane, t, sx);
+            case 5 * 32 + 3: return row_uniform_half_lds<T, 2, 3>(A, c, lane, t, sx);
+            default: return row_uniform_half_lds<T, 0, 0>(A, c, lane, t, sx);
+            }
+        }
+    }
+    switch (A.uwv / V) {
+    case 2: return row_uniform_lds<T, 2>(A, c, lane, t, sx);
+    case 3: return row_uniform_lds<T, 3>(A, c, lane, t, sx);
+    case 4: return row_uniform_lds<T, 4>(A, c, lane, t, sx);
+    case 7: return row_uniform_lds<T, 7>(A, c, lane, t, sx);
+    case 14: return row_uniform_lds<T, 14>(A, c, lane, t, sx);
+    default: return row_uniform_lds<T, 0>(A, c, lane, t, sx);
+    }
+}
+
 // (A x)_row for the row of this lane in slice c (c < nslices).
 template <typename T>
 __device__ inline double slice_row(const Sell<T>& A, int64_t c, int lane, const T* __restrict__ x)
@@ -494,9 +622,22 @@ __global__ __launch_bounds__(kRowBlock) void k_spmv(Sell<T> A, const T* __restri
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
     constexpr int kSlicesPerTile = kRowBlock / kSlice;
     // one tile (4 slices, one per wavefront) per workgroup
-    const int64_t c = xcd_block_tile() * kSlicesPerTile + wave;
-    if (c >= A.nslices) return;
-    const double acc = slice_row<T>(A, c, lane, x);
+    const int64_t tile = xcd_block_tile();
+    const int64_t c = tile * kSlicesPerTile + wave;
+    double acc;
+    bool staged = false;
+    if constexpr (sizeof(T) == 8) staged = A.lds_n > 0;   // FP32 views never stage
+    if (staged) {
+        extern __shared__ double lds_dyn[];
+        T* sx = reinterpret_cast<T*>(lds_dyn);
+        stage_x<T>(A, tile * kRowBlock, x, sx);
+        __syncthreads();
+        if (c >= A.nslices) return;
+        acc = uniform_row_lds<T>(A, c, lane, (int)threadIdx.x, sx);
+    } else {
+        if (c >= A.nslices) return;
+        acc = slice_row<T>(A, c, lane, x);
+    }
     const int64_t row = c * kSlice + lane;
     if (row < A.n) {
         const T p = (T)acc;
@@ -522,10 +663,21 @@ __global__ __launch_bounds__(kRowBlock) void k_residual(Sell<double> A, const do
     const int64_t ntiles = (A.nslices + kSlicesPerTile - 1) / kSlicesPerTile;
     const TileRange tr = xcd_tiles(ntiles);
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    extern __shared__ double lds_dyn[];
     for (int64_t t = tr.first; t < tr.end; t += tr.step) {
         const int64_t c = t * kSlicesPerTile + wave;
-        if (c >= A.nslices) break;
-        const double ax = slice_row<double>(A, c, lane, x);
+        double ax = 0.0;
+        if (A.lds_n > 0) {
+            // every wave of the workgroup reaches both barriers of every tile
+            __syncthreads();
+            stage_x<double>(A, t * kRowBlock, x, lds_dyn);
+            __syncthreads();
+            if (c >= A.nslices) continue;
+            ax = uniform_row_lds<double>(A, c, lane, (int)threadIdx.x, lds_dyn);
+        } else {
+            if (c >= A.nslices) break;
+            ax = slice_row<double>(A, c, lane, x);
+        }
         const int64_t row = c * kSlice + lane;
         if (row < A.n) {
             const double bi = b[row];
@@ -556,10 +708,21 @@ __global__ __launch_bounds__(kRowBlock) void k_pcg_spmv(Sell<double> A, const do
     const int64_t ntiles = (A.nslices + kSlicesPerTile - 1) / kSlicesPerTile;
     const TileRange tr = xcd_tiles(ntiles);
     double acc[1] = {0.0};
+    extern __shared__ double lds_dyn[];
     for (int64_t t = tr.first; t < tr.end; t += tr.step) {
         const int64_t c = t * kSlicesPerTile + wave;
-        if (c >= A.nslices) break;
-        const double ap = slice_row<double>(A, c, lane, p);
+        double ap = 0.0;
+        if (A.lds_n > 0) {
+            // every wave of the workgroup reaches both barriers of every tile
+            __syncthreads();
+            stage_x<double>(A, t * kRowBlock, p, lds_dyn);
+            __syncthreads();
+            if (c >= A.nslices) continue;
+            ap = uniform_row_lds<double>(A, c, lane, (int)threadIdx.x, lds_dyn);
+        } else {
+            if (c >= A.nslices) break;
+            ap = slice_row<double>(A, c, lane, p);
+        }
         const int64_t row = c * kSlice + lane;
         if (row < A.n) {
             q[row] = ap;
@@ -688,18 +851,49 @@ int num_cus()
     return cus;
 }
 
-int resident_blocks(const void* kernel, int threads)
+int resident_blocks(const void* kernel, int threads, size_t dyn_lds)
 {
     static std::mutex mu;
-    static std::unordered_map<const void*, int> cache;
+    static std::map<std::pair<const void*, size_t>, int> cache;
     std::lock_guard<std::mutex> lock(mu);
-    auto it = cache.find(kernel);
+    const auto key = std::make_pair(kernel, dyn_lds);
+    auto it = cache.find(key);
     if (it != cache.end()) return it->second;
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, threads, 0) != hipSuccess || nb < 1)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, threads, dyn_lds) != hipSuccess ||
+        nb < 1)
         nb = 1;
-    cache.emplace(kernel, nb);
+    cache.emplace(key, nb);
     return nb;
+}
+
+void plan_lds(sspcg_matrix* A)
+{
+    A->lds_n = A->ncl = A->lds_w = 0;
+    if (!A->uniform || A->uw < 1) return;
+    const int32_t* o = A->uoff_host;
+    int j = -1;
+    int run[kMaxUnion];
+    for (int k = 0; k < A->uw; ++k) {
+        if (k == 0 || o[k] != o[k - 1] + 1) {
+            ++j;
+            A->cl_lo[j] = o[k];
+            A->cl_w[j] = kRowBlock;
+        } else {
+            ++A->cl_w[j];
+        }
+        run[k] = j;
+    }
+    const int ncl = j + 1;
+    if (ncl > kMaxWindows) return;   // too many windows: gathers from memory
+    int w = 0;
+    for (int r = 0; r < ncl; ++r) w = std::max(w, A->cl_w[r]);
+    if (w > 2 * kRowBlock) return;   // a run longer than the tile: not worth staging
+    for (int k = 0; k < A->uw; ++k) A->lds_k[k] = run[k] * w + (o[k] - A->cl_lo[run[k]]);
+    for (int k = A->uw; k < kMaxUnion; ++k) A->lds_k[k] = A->lds_k[A->uw - 1];
+    A->ncl = ncl;
+    A->lds_w = w;
+    A->lds_n = ncl * w;
 }
 
 int persistent_grid(int64_t ntiles, int blocks_per_cu, int resident)
@@ -728,6 +922,15 @@ static Sell<T> make_view(const sspcg_matrix* A, int uwv, const T* val, const T* 
     S.uwv = uwv;
     S.usym = A->usym;
     std::copy(A->uoff_host, A->uoff_host + kMaxUnion, S.uo);
+    // LDS staging pays in FP64, where the gathers keep the address units
+    // busy; FP32 gathers move half the bytes and are faster straight from
+    // memory (124 vs 181 us at 192^3, 27 points)
+    S.lds_n = sizeof(T) == 8 ? A->lds_n : 0;
+    S.ncl = A->ncl;
+    S.lds_w = A->lds_w;
+    std::copy(A->cl_lo, A->cl_lo + kMaxUnion, S.cl_lo);
+    std::copy(A->cl_w, A->cl_w + kMaxUnion, S.cl_w);
+    std::copy(A->lds_k, A->lds_k + kMaxUnion, S.lds_k);
     S.nslices = A->nslices;
     S.slice_ptr = A->slice_ptr;
     S.slice_aux = A->slice_aux;
@@ -760,11 +963,15 @@ static int64_t spmv_tiles(const sspcg_matrix* A)
 // Persistent grid for the SpMV kernels that also reduce: all workgroups
 // resident at once.
 template <typename K>
-static int spmv_reduce_grid(const sspcg_matrix* A, K kernel)
+static int spmv_reduce_grid(const sspcg_matrix* A, K kernel, size_t dyn_lds)
 {
-    const int resident = resident_blocks(reinterpret_cast<const void*>(kernel), kRowBlock);
+    const int resident = resident_blocks(reinterpret_cast<const void*>(kernel), kRowBlock, dyn_lds);
     return persistent_grid(spmv_tiles(A), 8, resident);
 }
+
+// Dynamic LDS of the SpMV kernels: the staged windows of x.
+template <typename T>
+static size_t lds_bytes(const sspcg_matrix* A) { return sizeof(T) * (size_t)sell_view<T>(A).lds_n; }
 
 int matrix_check_symmetric(const sspcg_matrix* A, const double* val, bool* sym, hipStream_t st)
 {
@@ -940,15 +1147,16 @@ int launch_spmv(const sspcg_matrix* A, int mode, const T* x, T* y, const T* zpre
 {
     const Sell<T> S = sell_view<T>(A);
     const int64_t G = spmv_tiles(A);
+    const size_t lds = lds_bytes<T>(A);
     if (mode == 0)
-        hipLaunchKernelGGL((k_spmv<T, 0>), dim3(G), dim3(kRowBlock), 0, st, S, x, y, zprev, znext,
-                           c1, c2, c3, ctrl);
+        hipLaunchKernelGGL((k_spmv<T, 0>), dim3(G), dim3(kRowBlock), lds, st, S, x, y, zprev,
+                           znext, c1, c2, c3, ctrl);
     else if (mode == 1)
-        hipLaunchKernelGGL((k_spmv<T, 1>), dim3(G), dim3(kRowBlock), 0, st, S, x, y, zprev, znext,
-                           c1, c2, c3, ctrl);
+        hipLaunchKernelGGL((k_spmv<T, 1>), dim3(G), dim3(kRowBlock), lds, st, S, x, y, zprev,
+                           znext, c1, c2, c3, ctrl);
     else
-        hipLaunchKernelGGL((k_spmv<T, 2>), dim3(G), dim3(kRowBlock), 0, st, S, x, y, zprev, znext,
-                           c1, c2, c3, ctrl);
+        hipLaunchKernelGGL((k_spmv<T, 2>), dim3(G), dim3(kRowBlock), lds, st, S, x, y, zprev,
+                           znext, c1, c2, c3, ctrl);
     SSPCG_LAUNCHED("k_spmv");
     return SSPCG_OK;
 }
@@ -964,8 +1172,9 @@ int launch_residual(const sspcg_matrix* A, const double* x, const double* b, TR*
 {
     const Sell<double> S = sell_view<double>(A);
     const TR* dinvT = sell_view<TR>(A).dinv;
-    const int G = spmv_reduce_grid(A, k_residual<TR>);
-    hipLaunchKernelGGL((k_residual<TR>), dim3(G), dim3(kRowBlock), 0, st, S, x, b, r, z1, dinvT,
+    const size_t lds = lds_bytes<double>(A);
+    const int G = spmv_reduce_grid(A, k_residual<TR>, lds);
+    hipLaunchKernelGGL((k_residual<TR>), dim3(G), dim3(kRowBlock), lds, st, S, x, b, r, z1, dinvT,
                        partials);
     SSPCG_LAUNCHED("k_residual");
     *G_out = G;
@@ -980,8 +1189,9 @@ template int launch_residual<float>(const sspcg_matrix*, const double*, const do
 int launch_pcg_spmv(const sspcg_matrix* A, const double* p, double* q, double* partials,
                     int* G_out, const Ctrl* ctrl, hipStream_t st)
 {
-    const int G = spmv_reduce_grid(A, k_pcg_spmv);
-    hipLaunchKernelGGL(k_pcg_spmv, dim3(G), dim3(kRowBlock), 0, st, sell_view<double>(A), p, q,
+    const size_t lds = lds_bytes<double>(A);
+    const int G = spmv_reduce_grid(A, k_pcg_spmv, lds);
+    hipLaunchKernelGGL(k_pcg_spmv, dim3(G), dim3(kRowBlock), lds, st, sell_view<double>(A), p, q,
                        partials, ctrl);
     SSPCG_LAUNCHED("k_pcg_spmv");
     *G_out = G;
