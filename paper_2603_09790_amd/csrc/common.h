@@ -79,6 +79,7 @@ struct Sell {
     // kMaxWindows runs, or the layout is not uniform).
     int32_t lds_n;              // staged elements per tile (ncl * lds_w)
     int32_t ncl, lds_w;         // runs (windows), LDS slot length (the longest window)
+    int32_t lds_self;           // LDS index of x[row] for tile row 0 (the offset 0)
     int32_t cl_lo[32], cl_w[32];   // first offset and length of each window
     int32_t lds_k[32];          // LDS index of entry k for tile row 0 (stored pads: any window)
     int64_t nslices;

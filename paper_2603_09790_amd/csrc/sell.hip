@@ -625,6 +625,7 @@ __global__ __launch_bounds__(kRowBlock) void k_spmv(Sell<T> A, const T* __restri
     const int64_t tile = xcd_block_tile();
     const int64_t c = tile * kSlicesPerTile + wave;
     double acc;
+    T xself = (T)0;   // x[row] for the epilogue
     bool staged = false;
     if constexpr (sizeof(T) == 8) staged = A.lds_n > 0;   // FP32 views never stage
     if (staged) {
@@ -634,6 +635,7 @@ __global__ __launch_bounds__(kRowBlock) void k_spmv(Sell<T> A, const T* __restri
         __syncthreads();
         if (c >= A.nslices) return;
         acc = uniform_row_lds<T>(A, c, lane, (int)threadIdx.x, sx);
+        if (MODE >= 1) xself = sx[A.lds_self + threadIdx.x];   // staged with offset 0
     } else {
         if (c >= A.nslices) return;
         acc = slice_row<T>(A, c, lane, x);
@@ -643,8 +645,9 @@ __global__ __launch_bounds__(kRowBlock) void k_spmv(Sell<T> A, const T* __restri
         const T p = (T)acc;
         y[row] = p;
         if (MODE >= 1) {
+            if (!staged) xself = x[row];
             const double t1 = (double)A.dinv[row] * (double)p;
-            double z = c1 * t1 - c2 * (double)x[row];
+            double z = c1 * t1 - c2 * (double)xself;
             if (MODE == 2) z -= c3 * (double)zprev[row];
             znext[row] = (T)z;
         }
@@ -891,6 +894,11 @@ void plan_lds(sspcg_matrix* A)
     if (w > 2 * kRowBlock) return;   // a run longer than the tile: not worth staging
     for (int k = 0; k < A->uw; ++k) A->lds_k[k] = run[k] * w + (o[k] - A->cl_lo[run[k]]);
     for (int k = A->uw; k < kMaxUnion; ++k) A->lds_k[k] = A->lds_k[A->uw - 1];
+    // the element x[row] itself, for the epilogue of the matrix powers kernel
+    A->lds_self = -1;
+    for (int k = 0; k < A->uw; ++k)
+        if (o[k] == 0) A->lds_self = A->lds_k[k];
+    if (A->lds_self < 0) return;   // no diagonal offset (cannot happen: the diagonal is stored)
     A->ncl = ncl;
     A->lds_w = w;
     A->lds_n = ncl * w;
@@ -928,6 +936,7 @@ static Sell<T> make_view(const sspcg_matrix* A, int uwv, const T* val, const T* 
     S.lds_n = sizeof(T) == 8 ? A->lds_n : 0;
     S.ncl = A->ncl;
     S.lds_w = A->lds_w;
+    S.lds_self = A->lds_self;
     std::copy(A->cl_lo, A->cl_lo + kMaxUnion, S.cl_lo);
     std::copy(A->cl_w, A->cl_w + kMaxUnion, S.cl_w);
     std::copy(A->lds_k, A->lds_k + kMaxUnion, S.lds_k);
