@@ -621,3 +621,49 @@ def test_generic_stencil_rows(kind, N, full):
     xo, ro = oracle.sspcg(A, b, s=4, sweeps=3, interval=interval, tol=1e-30, max_outer=15)
     assert ig["outer_iters"] == ro["iters"] == 15
     assert np.linalg.norm(host(xg) - xo) <= 1e-10 * np.linalg.norm(xo)
+
+
+def banded_csr(n, offsets, seed):
+    """Symmetric, diagonally dominant matrix whose rows all use the offsets
+    +-o (o in offsets) and 0: a uniform layout whose offset list has one
+    run of consecutive values per isolated offset."""
+    import scipy.sparse as sp
+    rng = np.random.default_rng(seed)
+    diags, offs = [], []
+    for o in offsets:
+        v = rng.uniform(-1.0, -0.1, n - o)
+        diags += [v, v]
+        offs += [o, -o]
+    M = sp.diags(diags, offs, shape=(n, n)).tocsr()
+    d = np.asarray(abs(M).sum(axis=1)).ravel() + 1.0
+    M = (M + sp.diags(d)).tocsr()
+    M.sort_indices()
+    return si.CSR(n, M.indptr.astype(np.int32), M.indices.astype(np.int32), M.data.copy(),
+                  (1, 1, n))
+
+
+@pytest.mark.parametrize("nruns", [11, 13])
+@pytest.mark.parametrize("full", [False, True])
+def test_many_offset_runs(nruns, full):
+    """2k+1 isolated offsets (a mirrored list always has an odd number of
+    runs): up to 12 runs x is staged in LDS (FP64), beyond that the rows
+    gather from memory; both must give the oracle's product and iterates."""
+    k = (nruns - 1) // 2
+    offsets = [3 * (i + 1) + i * i for i in range(k)]            # no two consecutive
+    n = 64 * 37 + 11
+    A = banded_csr(n, offsets, seed=46 + nruns)
+    M = P.Matrix.from_csr(A, fp32=True, full_storage=full, device=DEV)
+    assert M.info()["symmetric"] == (0 if full else 1)
+    x = np.random.default_rng(47).normal(size=A.n)
+    y = host(P.spmv(M, gpu(x)))
+    ref = oracle.spmv(A, x)
+    absA = A.__class__(A.n, A.row_ptr, A.col, np.abs(A.val), A.shape3)
+    assert np.all(np.abs(y - ref) <= 1e-14 * oracle.spmv(absA, np.abs(x)))
+    x32 = x.astype(np.float32)
+    assert np.array_equal(host(P.spmv(M, gpu(x32))), oracle.spmv_f32(A, A.val.astype(np.float32), x32))
+    b = si.rhs_uniform(A.n)
+    interval = si.lanczos_bounds(A)
+    xg, ig = P.solve(M, gpu(b), s=4, sweeps=3, interval=interval, tol=1e-30, max_outer=12)
+    xo, ro = oracle.sspcg(A, b, s=4, sweeps=3, interval=interval, tol=1e-30, max_outer=12)
+    assert ig["outer_iters"] == ro["iters"] == 12
+    assert np.linalg.norm(host(xg) - xo) <= 1e-10 * np.linalg.norm(xo)
