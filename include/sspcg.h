@@ -149,14 +149,17 @@ void sspcg_default_params(sspcg_params* p);
  *   double[nnz]): CSR with row_ptr[0] = 0, increasing row pointers, columns in
  *   [0, n) and every diagonal entry stored.  Column order inside a row fixes
  *   the summation order of the SpMV.
- * The library allocates device memory for its sliced layout (64-row slices,
- * each stored column-major and padded to its longest row), the Jacobi
+ * The library allocates device memory for its sliced layout, the Jacobi
  * scaling 1/diag(A) and, with SSPCG_MATRIX_FP32, FP32 copies of both; it
  * frees them in sspcg_matrix_destroy.  The call synchronizes `stream`.
- * A stencil-like matrix (one list of at most 32 column offsets fits every
- * row) that is symmetric bit for bit is stored as its diagonal and upper
- * triangle only, which halves the values the SpMV streams; the product is
- * the same, term by term and in the same order.  SSPCG_MATRIX_FULL_STORAGE
+ * Layout: 64-row slices, one row per lane.  A slice whose rows share one
+ * list of at most 32 column offsets (col - row) stores that list once and
+ * no column indices; other slices keep explicit columns, padded to their
+ * longest row.  When one list fits every row (structured-grid stencils) the
+ * whole matrix is stored against it; if A is then also symmetric bit for bit,
+ * only its diagonal and upper triangle are stored, which halves the values
+ * the SpMV streams.  Every layout sums each row's entries in CSR order, so
+ * the product does not depend on the layout.  SSPCG_MATRIX_FULL_STORAGE
  * keeps both triangles (for later non-symmetric value updates).
  * Solves use only the library's copy, but sspcg_matrix_update_values,
  * sspcg_csr_value_grad and the diffusion calls read the caller's row_ptr and
@@ -252,7 +255,10 @@ int sspcg_interval(const sspcg_matrix* A, int32_t method, int32_t steps, double 
 size_t sspcg_kernel_work_bytes(int32_t s);
 
 /* y = A x (x, y device, dtype elements; F32 needs SSPCG_MATRIX_FP32: values
- * and x in FP32, products and sum in FP64, one rounding to FP32). */
+ * and x in FP32, products and sum in FP64, one rounding to FP32).  x should
+ * be finite: the offset-list layouts multiply stored zeros by neighbouring
+ * elements of x, so a NaN or Inf in x can also reach rows without an entry
+ * in its column (the solvers stop with SSPCG_ERR_NONFINITE either way). */
 int sspcg_spmv(const sspcg_matrix* A, int32_t dtype, const void* x, void* y, sspcg_stream stream);
 
 /* Algorithm 2 for the residual r: Z = [z_1..z_s] and P = [p_1..p_{s+1}]
