@@ -41,7 +41,7 @@
 extern "C" {
 #endif
 
-#define SSPCG_ABI_VERSION 1
+#define SSPCG_ABI_VERSION 2
 #define SSPCG_MAX_S 16          /* largest supported step size s */
 
 typedef void* sspcg_stream;     /* hipStream_t */
