@@ -643,12 +643,16 @@ __global__ __launch_bounds__(kRowBlock) void k_spmv(Sell<T> A, const T* __restri
     const int64_t row = c * kSlice + lane;
     if (row < A.n) {
         const T p = (T)acc;
-        y[row] = p;
+        // y (a column of AZ) is next read by the Gram kernels, long after
+        // it has left the caches, and z_{q-1} is dead after this step: both
+        // bypass cache allocation; z_{q+1} and dinv are read again by the
+        // next launch and stay cached
+        __builtin_nontemporal_store(p, y + row);
         if (MODE >= 1) {
             if (!staged) xself = x[row];
             const double t1 = (double)A.dinv[row] * (double)p;
             double z = c1 * t1 - c2 * (double)xself;
-            if (MODE == 2) z -= c3 * (double)zprev[row];
+            if (MODE == 2) z -= c3 * (double)__builtin_nontemporal_load(zprev + row);
             znext[row] = (T)z;
         }
     }
