@@ -11,9 +11,13 @@
 // FP32), and the gathers x[row + o_k] of a wave are contiguous too.  A row
 // without an entry at offset o_k holds an exact zero there and gathers its
 // own element instead.  Slices whose offset union is too long keep explicit
-// columns (64 indices per entry k), padded to the longest row.  In both
-// kinds the entries of a row keep their CSR order, which is the summation
-// order, and a zero adds nothing: the sum is the CSR sum.
+// columns (64 indices per entry k), padded to the longest row.  When one
+// list fits all slices the matrix uses the uniform layout instead (one
+// global list, 16-byte value groups, optionally one triangle of a
+// symmetric matrix, and in FP64 the gathered parts of x staged in LDS; see
+// Sell in common.h).  In every kind the entries of a row keep their CSR
+// order, which is the summation order, and a zero adds nothing (for finite
+// x): the sum is the CSR sum.
 
 #include <algorithm>
 #include <climits>
