@@ -186,10 +186,13 @@ __device__ inline void block_partials(double (&acc)[K], double* __restrict__ par
 }
 
 // Sum of partials[e * G + 0 .. G-1] by one wavefront in a fixed order.
+// Unrolled so that a lane's loads are in flight together; each lane still
+// adds its values in order, so the result does not depend on the unrolling.
 __device__ inline double wave_finish(const double* __restrict__ partials, int e, int G)
 {
     const int lane = threadIdx.x & (kWave - 1);
     double s = 0.0;
+#pragma unroll 8
     for (int g = lane; g < G; g += kWave) s += partials[(int64_t)e * G + g];
     return wave_sum(s);
 }
