@@ -122,10 +122,12 @@ def main() -> int:
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-profile", action="store_true",
                     help="time without the per-phase HIP events")
-    ap.add_argument("--mode", choices=["solve", "kernels", "paper", "configs"], default="solve",
+    ap.add_argument("--mode", choices=["solve", "kernels", "paper", "configs", "seeds"],
+                    default="solve",
                     help="kernels: a few launches of each hot kernel on the workload and a "
                          "copy kernel of known size (for rocprofv3 counter passes); paper: the "
-                         "paper's Gram-solve experiments on its own workload shape")
+                         "paper's Gram-solve experiments on its own workload shape; seeds: the "
+                         "FP64 and mixed solves for several right-hand sides")
     ap.add_argument("--paper-N", type=int, default=200)
     ap.add_argument("--paper-out", default=None,
                     help="paper mode: also write the per-iteration histories to this JSON file")
@@ -150,6 +152,9 @@ def main() -> int:
 
     if args.mode == "configs":
         print(json.dumps(other_configs(P, torch, dev, args)), flush=True)
+        return 0
+    if args.mode == "seeds":
+        print(json.dumps(seed_spread(P, torch, dev, args)), flush=True)
         return 0
     if args.mode == "paper":
         out = paper_experiments(P, torch, dev, args)
@@ -235,14 +240,20 @@ def main() -> int:
                    "interval": list(interval), "layout_slots": info_m["slots"],
                    "symmetric_storage": sym},
         "fp64": {"time_s": fp64_s, "outer_iters": last["outer_iters"], "relres": last["relres"],
-                 "status": last["status_name"]},
+                 "status": last["status_name"],
+                 "ms_per_outer_iter": 1e3 * fp64_s / max(last["outer_iters"], 1)},
     }
     if not args.no_mixed:
         mx_s = float(np.median([r[2]["device_ms"] for r in recs])) / 1e3
         lm = recs[-1][2]
+        # the iteration counts with two FGS sweeps move with rounding (see
+        # --mode seeds); the time per iteration does not
+        per_inner = 1e3 * mx_s / max(lm["outer_iters"], 1)
         out["mixed"] = {"time_s": mx_s, "refinements": lm["refinements"],
                         "inner_iters": lm["outer_iters"], "relres_true": lm["relres"],
-                        "speedup_vs_fp64": fp64_s / mx_s, "status": lm["status_name"]}
+                        "speedup_vs_fp64": fp64_s / mx_s, "status": lm["status_name"],
+                        "ms_per_inner_iter": per_inner,
+                        "speedup_per_iteration": out["fp64"]["ms_per_outer_iter"] / per_inner}
     if not args.no_profile:
         pr = last["profile"]
         sp = pr["spmv"]
@@ -336,6 +347,39 @@ def counter_traffic():
         return rec["traffic_bytes_per_launch"]
     except (OSError, KeyError, ValueError):
         return None
+
+
+def seed_spread(P, torch, dev, args, nseeds=5):
+    """FP64 and mixed solves of the 192^3 system for nseeds right-hand sides
+    b ~ N(0,1) (the benchmark's seed and the next ones): iteration counts and
+    times to tolerance, whose spread shows how much of a single run's count
+    is rounding-driven."""
+    import sspcg_inputs as si
+    A, _, interval = build_workload(args.N)
+    M = P.Matrix.from_csr(A, fp32=True, device=dev)
+    opts = dict(s=args.s, sweeps=args.sweeps, interval=interval, tol=args.tol)
+    runs = []
+    for k in range(nseeds):
+        b = torch.from_numpy(si.rhs_normal(A.n, si.SEED_RHS + k)).to(dev)
+        if k == 0:
+            P.solve(M, b, **opts)   # warm-up
+        _, i64 = P.solve(M, b, **opts)
+        _, imx = P.solve(M, b, precision="mixed", **opts)
+        r = {"seed": si.SEED_RHS + k, "fp64_s": i64["device_ms"] / 1e3,
+             "fp64_outer": i64["outer_iters"], "fp64_status": i64["status_name"],
+             "mixed_s": imx["device_ms"] / 1e3, "mixed_inner": imx["outer_iters"],
+             "mixed_refinements": imx["refinements"], "mixed_status": imx["status_name"],
+             "speedup": i64["device_ms"] / imx["device_ms"]}
+        runs.append(r)
+        log(f"[seeds] {r}")
+
+    def stats(key):
+        v = np.array([r[key] for r in runs], dtype=float)
+        return {"mean": float(v.mean()), "min": float(v.min()), "max": float(v.max())}
+
+    return {"mode": "seeds", "workload": f"27-point variable-coefficient diffusion {args.N}^3",
+            "s": args.s, "sweeps": args.sweeps, "tol": args.tol, "runs": runs,
+            **{k: stats(k) for k in ("fp64_s", "fp64_outer", "mixed_s", "mixed_inner", "speedup")}}
 
 
 def other_configs(P, torch, dev, args):

@@ -103,7 +103,11 @@ __global__ __launch_bounds__(kRowBlock) void k_update_gram(int64_t n, int64_t ld
     block_partials<K, kRowBlock>(acc, partials);
 }
 
-template <int S, typename T>
+// R consecutive rows per thread, read as one R-wide vector per column (the
+// FP32 blocks use R = 4: a 4-byte load per row and column leaves the kernel
+// limited by load instructions rather than bytes).  Rows are summed in order
+// within a thread.
+template <int S, typename T, int R>
 __global__ __launch_bounds__(kRowBlock) void k_gram_rect(int64_t n, int64_t ld,
                                                          const T* __restrict__ Q,
                                                          const T* __restrict__ AZ,
@@ -115,26 +119,56 @@ __global__ __launch_bounds__(kRowBlock) void k_gram_rect(int64_t n, int64_t ld,
     double acc[K];
 #pragma unroll
     for (int e = 0; e < K; ++e) acc[e] = 0.0;
-    const int64_t ntiles = (n + kRowBlock - 1) / kRowBlock;
-    const TileRange tr = xcd_tiles(ntiles);
-    for (int64_t t = tr.first; t < tr.end; t += tr.step) {
-        const int64_t i = t * kRowBlock + threadIdx.x;
-        if (i >= n) break;
-        double q[S], az[S];
-#pragma unroll
-        for (int j = 0; j < S; ++j) {
-            q[j] = (double)ldnt(Q + j * ld + i);
-            az[j] = (double)ldnt(AZ + j * ld + i);
-        }
+    auto add_row = [&](const double (&q)[S], const double (&az)[S]) {
 #pragma unroll
         for (int a = 0; a < S; ++a)
 #pragma unroll
             for (int b = 0; b < S; ++b) acc[a * S + b] = fma(q[a], az[b], acc[a * S + b]);
+    };
+    constexpr int64_t kRows = (int64_t)kRowBlock * R;
+    const int64_t ntiles = (n + kRows - 1) / kRows;
+    const TileRange tr = xcd_tiles(ntiles);
+    for (int64_t t = tr.first; t < tr.end; t += tr.step) {
+        const int64_t i = t * kRows + (int64_t)threadIdx.x * R;
+        if (i >= n) break;
+        if constexpr (R > 1) {
+            if (i + R <= n) {
+                typedef T VT __attribute__((ext_vector_type(R)));
+                VT qv[S], azv[S];
+#pragma unroll
+                for (int j = 0; j < S; ++j) {
+                    qv[j] = ldnt(reinterpret_cast<const VT*>(Q + j * ld + i));
+                    azv[j] = ldnt(reinterpret_cast<const VT*>(AZ + j * ld + i));
+                }
+#pragma unroll
+                for (int e = 0; e < R; ++e) {
+                    double q[S], az[S];
+#pragma unroll
+                    for (int j = 0; j < S; ++j) {
+                        q[j] = (double)qv[j][e];
+                        az[j] = (double)azv[j][e];
+                    }
+                    add_row(q, az);
+                }
+                continue;
+            }
+        }
+        for (int e = 0; e < R && i + e < n; ++e) {
+            double q[S], az[S];
+#pragma unroll
+            for (int j = 0; j < S; ++j) {
+                q[j] = (double)ldnt(Q + j * ld + i + e);
+                az[j] = (double)ldnt(AZ + j * ld + i + e);
+            }
+            add_row(q, az);
+        }
     }
     block_partials<K, kRowBlock>(acc, partials);
 }
 
-template <int S, typename T>
+// R consecutive rows per thread as R-wide vectors (R = 16 bytes / element
+// when every column is 16-byte aligned), each row computed as with R = 1.
+template <int S, typename T, int R>
 __global__ __launch_bounds__(kRowBlock) void k_xr(int64_t n, int64_t ld, const T* __restrict__ Q,
                                                   const T* __restrict__ AQ,
                                                   const double* __restrict__ alpha,
@@ -148,22 +182,63 @@ __global__ __launch_bounds__(kRowBlock) void k_xr(int64_t n, int64_t ld, const T
 #pragma unroll
     for (int j = 0; j < S; ++j) al[j] = alpha[j];
     double acc[1] = {0.0};
-    const int64_t ntiles = (n + kRowBlock - 1) / kRowBlock;
+    constexpr int64_t kRows = (int64_t)kRowBlock * R;
+    const int64_t ntiles = (n + kRows - 1) / kRows;
     const TileRange tr = xcd_tiles(ntiles);
     for (int64_t t = tr.first; t < tr.end; t += tr.step) {
-        const int64_t i = t * kRowBlock + threadIdx.x;
+        const int64_t i = t * kRows + (int64_t)threadIdx.x * R;
         if (i >= n) break;
-        double qa = 0.0, aqa = 0.0;
+        if constexpr (R > 1) {
+            if (i + R <= n) {
+                typedef T VT __attribute__((ext_vector_type(R)));
+                double qa[R], aqa[R];
 #pragma unroll
-        for (int j = 0; j < S; ++j) {
-            qa = fma((double)ldnt(Q + j * ld + i), al[j], qa);
-            aqa = fma((double)ldnt(AQ + j * ld + i), al[j], aqa);
+                for (int e = 0; e < R; ++e) qa[e] = aqa[e] = 0.0;
+#pragma unroll
+                for (int j = 0; j < S; ++j) {
+                    const VT q = ldnt(reinterpret_cast<const VT*>(Q + j * ld + i));
+                    const VT aq = ldnt(reinterpret_cast<const VT*>(AQ + j * ld + i));
+#pragma unroll
+                    for (int e = 0; e < R; ++e) {
+                        qa[e] = fma((double)q[e], al[j], qa[e]);
+                        aqa[e] = fma((double)aq[e], al[j], aqa[e]);
+                    }
+                }
+                VT xv = *reinterpret_cast<const VT*>(x + i);
+                VT rv = *reinterpret_cast<const VT*>(r + i);
+#pragma unroll
+                for (int e = 0; e < R; ++e) {
+                    xv[e] = (T)((double)xv[e] + qa[e]);
+                    rv[e] = (T)((double)rv[e] - aqa[e]);
+                }
+                *reinterpret_cast<VT*>(x + i) = xv;
+                *reinterpret_cast<VT*>(r + i) = rv;
+                if (z1) {
+                    const VT dv = ldnt(reinterpret_cast<const VT*>(dinv + i));
+                    VT zv;
+#pragma unroll
+                    for (int e = 0; e < R; ++e) zv[e] = (T)((double)dv[e] * (double)rv[e]);
+                    stnt(reinterpret_cast<VT*>(z1 + i), zv);
+                }
+#pragma unroll
+                for (int e = 0; e < R; ++e) acc[0] = fma((double)rv[e], (double)rv[e], acc[0]);
+                continue;
+            }
         }
-        x[i] = (T)((double)x[i] + qa);
-        const T ri = (T)((double)r[i] - aqa);
-        r[i] = ri;
-        if (z1) stnt(z1 + i, (T)((double)ldnt(dinv + i) * (double)ri));
-        acc[0] = fma((double)ri, (double)ri, acc[0]);
+        for (int e = 0; e < R && i + e < n; ++e) {
+            const int64_t k = i + e;
+            double qa = 0.0, aqa = 0.0;
+#pragma unroll
+            for (int j = 0; j < S; ++j) {
+                qa = fma((double)ldnt(Q + j * ld + k), al[j], qa);
+                aqa = fma((double)ldnt(AQ + j * ld + k), al[j], aqa);
+            }
+            x[k] = (T)((double)x[k] + qa);
+            const T rk = (T)((double)r[k] - aqa);
+            r[k] = rk;
+            if (z1) stnt(z1 + k, (T)((double)ldnt(dinv + k) * (double)rk));
+            acc[0] = fma((double)rk, (double)rk, acc[0]);
+        }
     }
     block_partials<1, kRowBlock>(acc, partials);
 }
@@ -239,13 +314,25 @@ template <typename T>
 int launch_gram_rect(int64_t n, int s, const T* Q, const T* AZ, int64_t ld, double* partials,
                      int* G_out, const Ctrl* ctrl, hipStream_t st)
 {
+    // FP32 columns whose elements 4i.. are 16-byte aligned go 4 rows per
+    // thread; anything else one row per thread
+    constexpr int RV = sizeof(T) == 4 ? 4 : 1;
+    const bool vec = RV > 1 && ld % RV == 0 && reinterpret_cast<uintptr_t>(Q) % 16 == 0 &&
+                     reinterpret_cast<uintptr_t>(AZ) % 16 == 0;
+    const int64_t units = vec ? (n + RV - 1) / RV : n;
     int G = 0;
     switch (s) {
-#define X(S)                                                                                    \
-    case S:                                                                                     \
-        G = block_grid(n, k_gram_rect<S, T>);                                                   \
-        hipLaunchKernelGGL((k_gram_rect<S, T>), dim3(G), dim3(kRowBlock), 0, st, n, ld, Q, AZ, \
-                           partials, ctrl);                                                     \
+#define X(S)                                                                                   \
+    case S:                                                                                    \
+        if (vec) {                                                                             \
+            G = block_grid(units, k_gram_rect<S, T, RV>);                                      \
+            hipLaunchKernelGGL((k_gram_rect<S, T, RV>), dim3(G), dim3(kRowBlock), 0, st, n, ld, \
+                               Q, AZ, partials, ctrl);                                         \
+        } else {                                                                               \
+            G = block_grid(units, k_gram_rect<S, T, 1>);                                       \
+            hipLaunchKernelGGL((k_gram_rect<S, T, 1>), dim3(G), dim3(kRowBlock), 0, st, n, ld, \
+                               Q, AZ, partials, ctrl);                                         \
+        }                                                                                      \
         break;
         SSPCG_S_CASES(X)
 #undef X
@@ -263,13 +350,23 @@ int launch_xr(int64_t n, int s, const T* Q, const T* AQ, const double* alpha, in
               T* r, const T* dinv, T* z1, double* partials, int* G_out, const Ctrl* ctrl,
               hipStream_t st)
 {
+    constexpr int RV = 16 / (int)sizeof(T);
+    auto a16 = [](const void* p) { return reinterpret_cast<uintptr_t>(p) % 16 == 0; };
+    const bool vec = ld % RV == 0 && a16(Q) && a16(AQ) && a16(x) && a16(r) && a16(dinv) && a16(z1);
+    const int64_t units = vec ? (n + RV - 1) / RV : n;
     int G = 0;
     switch (s) {
 #define X(S)                                                                                   \
     case S:                                                                                    \
-        G = block_grid(n, k_xr<S, T>);                                                         \
-        hipLaunchKernelGGL((k_xr<S, T>), dim3(G), dim3(kRowBlock), 0, st, n, ld, Q, AQ, alpha, \
-                           x, r, dinv, z1, partials, ctrl);                                    \
+        if (vec) {                                                                             \
+            G = block_grid(units, k_xr<S, T, RV>);                                             \
+            hipLaunchKernelGGL((k_xr<S, T, RV>), dim3(G), dim3(kRowBlock), 0, st, n, ld, Q, AQ, \
+                               alpha, x, r, dinv, z1, partials, ctrl);                         \
+        } else {                                                                               \
+            G = block_grid(units, k_xr<S, T, 1>);                                              \
+            hipLaunchKernelGGL((k_xr<S, T, 1>), dim3(G), dim3(kRowBlock), 0, st, n, ld, Q, AQ, \
+                               alpha, x, r, dinv, z1, partials, ctrl);                         \
+        }                                                                                      \
         break;
         SSPCG_S_CASES(X)
 #undef X

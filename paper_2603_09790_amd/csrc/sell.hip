@@ -526,10 +526,11 @@ __device__ inline double row_uniform_lds(const Sell<T>& A, int64_t c, int lane, 
     return acc;
 }
 
-// Symmetric half storage, x from LDS (see row_uniform_half).
+// Symmetric half storage, x from LDS (see row_uniform_half).  The row's
+// first own entry is its diagonal; it is returned in dg.
 template <typename T, int H, int NV>
 __device__ inline double row_uniform_half_lds(const Sell<T>& A, int64_t c, int lane, int t,
-                                              const T* __restrict__ sx)
+                                              const T* __restrict__ sx, T& dg)
 {
     constexpr int V = HalfV<T>::value;
     typedef T VT __attribute__((ext_vector_type(V)));
@@ -549,6 +550,7 @@ __device__ inline double row_uniform_half_lds(const Sell<T>& A, int64_t c, int l
     const VT* vp = reinterpret_cast<const VT*>(A.val + c * sw) + lane;
     auto upper = [&](int j) {
         const VT v = vp[(int64_t)j * kSlice];
+        if (j == 0) dg = v[0];
 #pragma unroll
         for (int e = 0; e < V; ++e) {
             const int k = h + j * V + e;
@@ -567,25 +569,27 @@ __device__ inline double row_uniform_half_lds(const Sell<T>& A, int64_t c, int l
     return acc;
 }
 
+// (A x)_row from LDS-staged x.  dg receives the row's diagonal value with
+// the symmetric half storage and is left untouched otherwise.
 template <typename T>
 __device__ inline double uniform_row_lds(const Sell<T>& A, int64_t c, int lane, int t,
-                                         const T* __restrict__ sx)
+                                         const T* __restrict__ sx, T& dg)
 {
     constexpr int V = 16 / sizeof(T);
     if (A.usym) {
         if constexpr (sizeof(T) == 8) {
             switch (A.uw * 32 + A.uwv / 2) {
-            case 27 * 32 + 7: return row_uniform_half_lds<T, 13, 7>(A, c, lane, t, sx);
-            case 7 * 32 + 2: return row_uniform_half_lds<T, 3, 2>(A, c, lane, t, sx);
-            case 5 * 32 + 2: return row_uniform_half_lds<T, 2, 2>(A, c, lane, t, sx);
-            default: return row_uniform_half_lds<T, 0, 0>(A, c, lane, t, sx);
+            case 27 * 32 + 7: return row_uniform_half_lds<T, 13, 7>(A, c, lane, t, sx, dg);
+            case 7 * 32 + 2: return row_uniform_half_lds<T, 3, 2>(A, c, lane, t, sx, dg);
+            case 5 * 32 + 2: return row_uniform_half_lds<T, 2, 2>(A, c, lane, t, sx, dg);
+            default: return row_uniform_half_lds<T, 0, 0>(A, c, lane, t, sx, dg);
             }
         } else {
             switch (A.uw * 32 + A.uwv) {
-            case 27 * 32 + 14: return row_uniform_half_lds<T, 13, 14>(A, c, lane, t, sx);
-            case 7 * 32 + 4: return row_uniform_half_lds<T, 3, 4>(A, c, lane, t, sx);
-            case 5 * 32 + 3: return row_uniform_half_lds<T, 2, 3>(A, c, lane, t, sx);
-            default: return row_uniform_half_lds<T, 0, 0>(A, c, lane, t, sx);
+            case 27 * 32 + 14: return row_uniform_half_lds<T, 13, 14>(A, c, lane, t, sx, dg);
+            case 7 * 32 + 4: return row_uniform_half_lds<T, 3, 4>(A, c, lane, t, sx, dg);
+            case 5 * 32 + 3: return row_uniform_half_lds<T, 2, 3>(A, c, lane, t, sx, dg);
+            default: return row_uniform_half_lds<T, 0, 0>(A, c, lane, t, sx, dg);
             }
         }
     }
@@ -630,6 +634,7 @@ __global__ __launch_bounds__(kRowBlock) void k_spmv(Sell<T> A, const T* __restri
     const int64_t c = tile * kSlicesPerTile + wave;
     double acc;
     T xself = (T)0;   // x[row] for the epilogue
+    T dg = (T)0;      // the row's diagonal value, if the row function returns it
     bool staged = false;
     if constexpr (sizeof(T) == 8) staged = A.lds_n > 0;   // FP32 views never stage
     if (staged) {
@@ -638,7 +643,7 @@ __global__ __launch_bounds__(kRowBlock) void k_spmv(Sell<T> A, const T* __restri
         stage_x<T>(A, tile * kRowBlock, x, sx);
         __syncthreads();
         if (c >= A.nslices) return;
-        acc = uniform_row_lds<T>(A, c, lane, (int)threadIdx.x, sx);
+        acc = uniform_row_lds<T>(A, c, lane, (int)threadIdx.x, sx, dg);
         if (MODE >= 1) xself = sx[A.lds_self + threadIdx.x];   // staged with offset 0
     } else {
         if (c >= A.nslices) return;
@@ -649,12 +654,15 @@ __global__ __launch_bounds__(kRowBlock) void k_spmv(Sell<T> A, const T* __restri
         const T p = (T)acc;
         // y (a column of AZ) is next read by the Gram kernels, long after
         // it has left the caches, and z_{q-1} is dead after this step: both
-        // bypass cache allocation; z_{q+1} and dinv are read again by the
-        // next launch and stay cached
+        // bypass cache allocation; z_{q+1} is read again by the next launch
         __builtin_nontemporal_store(p, y + row);
         if (MODE >= 1) {
             if (!staged) xself = x[row];
-            const double t1 = (double)A.dinv[row] * (double)p;
+            // with the half storage the diagonal came with the row's values:
+            // its reciprocal (correctly rounded, as when dinv was formed)
+            // equals dinv[row] bit for bit and saves reading dinv
+            const double di = (staged && A.usym) ? 1.0 / (double)dg : (double)A.dinv[row];
+            const double t1 = di * (double)p;
             double z = c1 * t1 - c2 * (double)xself;
             if (MODE == 2) z -= c3 * (double)__builtin_nontemporal_load(zprev + row);
             znext[row] = (T)z;
@@ -684,7 +692,8 @@ __global__ __launch_bounds__(kRowBlock) void k_residual(Sell<double> A, const do
             stage_x<double>(A, t * kRowBlock, x, lds_dyn);
             __syncthreads();
             if (c >= A.nslices) continue;
-            ax = uniform_row_lds<double>(A, c, lane, (int)threadIdx.x, lds_dyn);
+            double dg;
+            ax = uniform_row_lds<double>(A, c, lane, (int)threadIdx.x, lds_dyn, dg);
         } else {
             if (c >= A.nslices) break;
             ax = slice_row<double>(A, c, lane, x);
@@ -729,7 +738,8 @@ __global__ __launch_bounds__(kRowBlock) void k_pcg_spmv(Sell<double> A, const do
             stage_x<double>(A, t * kRowBlock, p, lds_dyn);
             __syncthreads();
             if (c >= A.nslices) continue;
-            ap = uniform_row_lds<double>(A, c, lane, (int)threadIdx.x, lds_dyn);
+            double dg;
+            ap = uniform_row_lds<double>(A, c, lane, (int)threadIdx.x, lds_dyn, dg);
         } else {
             if (c >= A.nslices) break;
             ap = slice_row<double>(A, c, lane, p);

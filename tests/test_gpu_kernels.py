@@ -239,6 +239,36 @@ def test_xr_update(traced, key, k):
     assert abs(rr - oracle.dot(nx["r"], nx["r"])) <= 1e-12 * rr
 
 
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_xr_update_row_groups_match_single_rows(dtype):
+    """16-byte aligned columns take R rows per thread, others one row per
+    thread; every row's x, r and z1 are the same either way (only the sum
+    order of ||r||^2 differs)."""
+    A, _, _ = system("d27_17")   # n = 4913: a ragged tail for R = 2 and 4
+    M = P.Matrix.from_csr(A, fp32=True, device=DEV)
+    s, n = 6, A.n
+    ld = P.leading_dim(n)
+    rng = np.random.default_rng(12)
+    Q = gpu(rng.normal(size=(s, ld)), dtype)
+    AQ = gpu(rng.normal(size=(s, ld)), dtype)
+    alpha = gpu(rng.normal(size=s))
+    x0, r0 = rng.normal(size=n), rng.normal(size=n)
+    out = []
+    for offset in (0, 1):   # offset 1: x, r, z1 not 16-byte aligned
+        vecs = []
+        for v in (x0, r0, np.zeros(n)):
+            buf = torch.zeros(n + offset, dtype=dtype, device=DEV)
+            buf[offset:] = gpu(v, dtype)
+            vecs.append(buf[offset:])
+        rr = P.xr_update(M, Q, AQ, alpha, *vecs)
+        out.append([host(v) for v in vecs] + [rr])
+    for a, b in zip(out[0][:3], out[1][:3]):
+        assert np.array_equal(a, b)
+    assert abs(out[0][3] - out[1][3]) <= 1e-13 * out[1][3]
+    xr = x0 + host(Q)[:, :n].astype(float).T @ host(alpha)
+    assert np.abs(out[0][0] - xr).max() <= (1e-13 if dtype == torch.float64 else 1e-6) * np.abs(xr).max()
+
+
 @pytest.mark.parametrize("key", KEYS)
 @pytest.mark.parametrize("k", [0, 2, 7])
 def test_one_outer_iteration(traced, key, k):
@@ -286,6 +316,29 @@ def test_fp32_gram_kernels_match_upcast_oracle():
     Wr, br = oracle.gram(host(Qg), host(AQg), r)
     gram_close(host(W), Wr, host(Qg).astype(float), host(AQg).astype(float))
 
+
+
+@pytest.mark.parametrize("n,ld,offset", [
+    (2197, 2240, 0),     # 4 rows per thread, ragged tail of 1 row
+    (4098, 4160, 0),     # tail of 2 rows
+    (70001, 70016, 0),   # many 1024-row tiles and a tail
+    (4099, 4099, 0),     # ld not a multiple of 4: one row per thread
+    (4096, 4096, 1),     # columns not 16-byte aligned: one row per thread
+])
+def test_fp32_gram_rect_row_groups(n, ld, offset):
+    s = 5
+    rng = np.random.default_rng(n + offset)
+    Q = rng.normal(size=(s, n)).astype(np.float32)
+    AZ = rng.normal(size=(s, n)).astype(np.float32)
+
+    def on_device(X):
+        buf = torch.full((offset + s * ld,), float("nan"), dtype=torch.float32, device=DEV)
+        view = buf[offset:].view(s, ld)
+        view[:, :n] = gpu(X)
+        return view
+
+    B2 = P.gram_rect(n, on_device(Q), on_device(AZ))
+    gram_close(host(B2), oracle.gram_rect(Q, AZ), Q.astype(float), AZ.astype(float))
 
 # ------------------------------------------------------------- differentiation
 def test_diffusion_kernels_match_oracle():
