@@ -49,11 +49,15 @@ def spmv_bytes(n: int, nval: int, elem: int, col_frac: float) -> float:
     return elem * nval + 4 * col_frac * nval + 2 * n * elem
 
 
-def spmv_family_bytes(n: int, nval: int, s: int, elem: int, col_frac: float = 1.0) -> float:
+def spmv_family_bytes(n: int, nval: int, s: int, elem: int, col_frac: float = 1.0,
+                      dinv_read: bool = True) -> float:
     """Algorithmic bytes of one matrix powers kernel (s SpMV launches): s
-    SpMVs plus the epilogues, dinv read and z_{q+1} written for q < s (2 n
-    elem) and z_{q-1} read for 2 <= q < s (n elem)."""
-    epi = sum((2 if q == 1 else 3) * n * elem for q in range(1, s))
+    SpMVs plus the epilogues, z_{q+1} written and (dinv_read) dinv read for
+    q < s, and z_{q-1} read for 2 <= q < s (n elem each).  The symmetric half
+    storage streams each row's diagonal with its values, so its epilogue
+    forms 1/a_ii there instead of reading dinv."""
+    per = 2 if dinv_read else 1
+    epi = sum((per if q == 1 else per + 1) * n * elem for q in range(1, s))
     return s * spmv_bytes(n, nval, elem, col_frac) + epi
 
 
@@ -262,7 +266,7 @@ def main() -> int:
         # format itself has to stream (no column indices; one triangle of
         # values with the symmetric half storage)
         b_csr = csr_family_bytes(n, nnz, s, 8) / s
-        b_fmt = spmv_family_bytes(n, nval, s, 8, col_frac) / s
+        b_fmt = spmv_family_bytes(n, nval, s, 8, col_frac, dinv_read=not sym) / s
         t_launch = sp["ms"] / 1e3 / sp["launches"]
         achieved = b_csr / t_launch / 1e9
         fmt_gbs = b_fmt / t_launch / 1e9
@@ -539,6 +543,8 @@ def kernel_pass(P, torch, M, A, b, interval, args, col_frac, nval):
     alpha = torch.randn(s, dtype=torch.float64, device=M.device)
     r = torch.randn(n, dtype=torch.float64, device=M.device)
     xr_x = torch.zeros(n, dtype=torch.float64, device=M.device)
+    z1 = torch.empty_like(xr_x)
+    sym = bool(M.info()["symmetric"])
     ev = lambda: torch.cuda.Event(enable_timing=True)
     out = {}
 
@@ -558,11 +564,12 @@ def kernel_pass(P, torch, M, A, b, interval, args, col_frac, nval):
     timed("copy_1GiB", lambda: dst.copy_(src), 2 * COPY_BYTES)
     timed("spmv_f64", lambda: P.spmv(M, x), spmv_bytes(n, nval, 8, col_frac))
     timed("mpk_f64_s%d" % s, lambda: P.mpk(M, r, s, interval, ld=ld),
-          spmv_family_bytes(n, nval, s, 8, col_frac))
+          spmv_family_bytes(n, nval, s, 8, col_frac, dinv_read=not sym))
     timed("gram_update", lambda: P.block_update_gram(n, Zb, Qb, AZb, AQb, beta, r),
           (6 * s + 1) * 8 * n)
     timed("gram_rect", lambda: P.gram_rect(n, Qb, AZb), 2 * s * 8 * n)
-    timed("xr", lambda: P.xr_update(M, Qb, AQb, alpha, xr_x, r), (2 * s + 6) * 8 * n)
+    # as in the solve: z1 = M^{-1} r written as well
+    timed("xr", lambda: P.xr_update(M, Qb, AQb, alpha, xr_x, r, z1), (2 * s + 6) * 8 * n)
     if M.fp32:
         x32 = x.float()
         timed("spmv_f32", lambda: P.spmv(M, x32), spmv_bytes(n, nval, 4, col_frac))

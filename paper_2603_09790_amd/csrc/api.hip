@@ -379,7 +379,8 @@ int run_sspcg(const sspcg_matrix* A, const sspcg_params* p, const Workspace& w, 
     rc = enqueue_mpk<T>(A, s, p->basis, al, sg, Z, AZ, ld, ctrl, st);
     tm.start_mark(1, st);
     if (rc == SSPCG_OK)
-        rc = launch_update_gram<T>(n, s, Z, Q, AZ, AQ, nullptr, r, ld, part, &G, ctrl, st);
+        rc = launch_update_gram<T>(n, s, Z, Q, AZ, AQ, nullptr, r, nullptr, nullptr, ld, part, &G,
+                                   ctrl, st);
     tm.start_mark(2, st);
     if (rc == SSPCG_OK)
         rc = launch_fgs_step(s, 0, part, G, Wbuf, alpha, p->sweeps, p->sweep_tol, p->gram, ctrl,
@@ -389,7 +390,9 @@ int run_sspcg(const sspcg_matrix* A, const sspcg_params* p, const Workspace& w, 
     auto step = [&](int64_t k) -> int {
         int g = 0;
         tm.mark(k, 0, st);
-        int e = launch_xr<T>(n, s, Q, AQ, alpha, ld, x, r, dinv, Z, part, &g, ctrl, st);
+        // r and z_1 now; x += Q alpha rides on the next block update, which
+        // streams this Q anyway (or on the pending-x launch after the loop)
+        int e = launch_xr<T>(n, s, Q, AQ, alpha, ld, nullptr, r, dinv, Z, part, &g, ctrl, st);
         tm.mark(k, 1, st);
         if (e == SSPCG_OK) e = launch_norm_step(part, g, ctrl, dhist, st);
         tm.mark(k, 2, st);
@@ -401,7 +404,8 @@ int run_sspcg(const sspcg_matrix* A, const sspcg_params* p, const Workspace& w, 
             e = launch_fgs_step(s, 1, part, g, Wbuf, beta, p->sweeps, p->sweep_tol, p->gram, ctrl,
                                 dhist, st);
         tm.mark(k, 5, st);
-        if (e == SSPCG_OK) e = launch_update_gram<T>(n, s, Z, Q, AZ, AQ, beta, r, ld, part, &g, ctrl, st);
+        if (e == SSPCG_OK)
+            e = launch_update_gram<T>(n, s, Z, Q, AZ, AQ, beta, r, x, alpha, ld, part, &g, ctrl, st);
         tm.mark(k, 6, st);
         if (e == SSPCG_OK)
             e = launch_fgs_step(s, 0, part, g, Wbuf, alpha, p->sweeps, p->sweep_tol, p->gram, ctrl,
@@ -432,10 +436,12 @@ int run_sspcg(const sspcg_matrix* A, const sspcg_params* p, const Workspace& w, 
         rc = run_polled(ctrl, A->host_ctrl, batches * p->check_every, p->check_every, st, replay);
         (void)hipGraphExecDestroy(exec);
         (void)hipGraphDestroy(graph);
+        if (rc == SSPCG_OK) rc = launch_x_pending<T>(n, s, Q, alpha, ld, x, ctrl, st);
         return rc;
     }
     rc = run_polled(ctrl, A->host_ctrl, max_iter, p->check_every, st, step, on_batch);
     if (rc == SSPCG_OK) tm.fill(const_cast<sspcg_profile*>(&A->profile), s, A->host_ctrl[0].iter);
+    if (rc == SSPCG_OK) rc = launch_x_pending<T>(n, s, Q, alpha, ld, x, ctrl, st);
     return rc;
 }
 
@@ -1100,13 +1106,14 @@ int sspcg_block_update_gram(int64_t n, int32_t s, int32_t dtype, const void* Z, 
     if (dtype == SSPCG_F32)
         RETURN_IF(launch_update_gram<float>(n, s, static_cast<const float*>(Z), static_cast<float*>(Q),
                                             static_cast<const float*>(AZ), static_cast<float*>(AQ),
-                                            beta, static_cast<const float*>(r), ld, part, &G,
-                                            nullptr, st));
+                                            beta, static_cast<const float*>(r), nullptr, nullptr,
+                                            ld, part, &G, nullptr, st));
     else
         RETURN_IF(launch_update_gram<double>(n, s, static_cast<const double*>(Z),
                                              static_cast<double*>(Q), static_cast<const double*>(AZ),
                                              static_cast<double*>(AQ), beta,
-                                             static_cast<const double*>(r), ld, part, &G, nullptr,
+                                             static_cast<const double*>(r), nullptr, nullptr, ld,
+                                             part, &G, nullptr,
                                              st));
     return launch_gram_out(s, 0, part, G, W, b1, st);
     API_CATCH

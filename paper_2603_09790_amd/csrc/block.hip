@@ -34,7 +34,13 @@ __device__ inline void stnt(T* p, T v)
     __builtin_nontemporal_store(v, p);
 }
 
-template <int S, typename T, bool FIRST>
+// MODE 0: the first update (Q = Z, AQ = AZ).  MODE 1: Q = Z + Q beta,
+// AQ = AZ + AQ beta.  MODE 2: MODE 1 and, if ctrl->x_pending, the x update of
+// the previous outer iteration, x += Q alpha with the old Q streamed here
+// anyway, in the same arithmetic as k_xr; the solve's x/r update then
+// leaves x alone and never reads Q.  x is loaded with the row's other
+// operands, so its latency overlaps theirs.
+template <int S, typename T, int MODE>
 __global__ __launch_bounds__(kRowBlock) void k_update_gram(int64_t n, int64_t ld,
                                                            const T* __restrict__ Z,
                                                            T* __restrict__ Q,
@@ -42,6 +48,8 @@ __global__ __launch_bounds__(kRowBlock) void k_update_gram(int64_t n, int64_t ld
                                                            T* __restrict__ AQ,
                                                            const double* __restrict__ beta,
                                                            const T* __restrict__ r,
+                                                           T* __restrict__ x,
+                                                           const double* __restrict__ alpha,
                                                            double* __restrict__ partials,
                                                            const Ctrl* __restrict__ ctrl)
 {
@@ -50,16 +58,41 @@ __global__ __launch_bounds__(kRowBlock) void k_update_gram(int64_t n, int64_t ld
     double acc[K];
 #pragma unroll
     for (int e = 0; e < K; ++e) acc[e] = 0.0;
+    constexpr bool FIRST = MODE == 0;
+    bool pend = false;
+    double al[S];
+    if constexpr (MODE == 2) {
+        pend = ctrl->x_pending != 0;
+#pragma unroll
+        for (int j = 0; j < S; ++j) al[j] = alpha[j];
+    }
     const int64_t ntiles = (n + kRowBlock - 1) / kRowBlock;
     const TileRange tr = xcd_tiles(ntiles);
     for (int64_t t = tr.first; t < tr.end; t += tr.step) {
         const int64_t i = t * kRowBlock + threadIdx.x;
         if (i >= n) break;
+        // FP32: every load of the row is issued before its first store (the
+        // wait counter is shared by loads and stores, so a load queued behind
+        // a store also waits for the store; 271 -> 217 us per FP32 update at
+        // 192^3).  FP64 loads Z and AZ column by column between the stores:
+        // holding all its operands at once costs a wave per SIMD.
+        constexpr bool kPreload = sizeof(T) == 4;
         double q[S], aq[S];
-        if (FIRST) {
+        T zv[S], azv[S];
+        T rv = (T)0;
+        if constexpr (kPreload) {
 #pragma unroll
             for (int j = 0; j < S; ++j) {
-                const T zj = ldnt(Z + j * ld + i), azj = ldnt(AZ + j * ld + i);
+                zv[j] = ldnt(Z + j * ld + i);
+                azv[j] = ldnt(AZ + j * ld + i);
+            }
+            rv = ldnt(r + i);
+        }
+        if constexpr (FIRST) {
+#pragma unroll
+            for (int j = 0; j < S; ++j) {
+                const T zj = kPreload ? zv[j] : ldnt(Z + j * ld + i);
+                const T azj = kPreload ? azv[j] : ldnt(AZ + j * ld + i);
                 stnt(Q + j * ld + i, zj);
                 stnt(AQ + j * ld + i, azj);
                 q[j] = (double)zj;
@@ -72,6 +105,9 @@ __global__ __launch_bounds__(kRowBlock) void k_update_gram(int64_t n, int64_t ld
                 qo[j] = (double)ldnt(Q + j * ld + i);
                 aqo[j] = (double)ldnt(AQ + j * ld + i);
             }
+            T xi = (T)0;
+            if constexpr (MODE == 2) xi = ldnt(x + i);
+            T qn[S], aqn[S];
 #pragma unroll
             for (int j = 0; j < S; ++j) {
                 double tq = 0.0, taq = 0.0;
@@ -80,15 +116,34 @@ __global__ __launch_bounds__(kRowBlock) void k_update_gram(int64_t n, int64_t ld
                     tq = fma(qo[l], beta[l * S + j], tq);
                     taq = fma(aqo[l], beta[l * S + j], taq);
                 }
-                const T qn = (T)((double)ldnt(Z + j * ld + i) + tq);
-                const T aqn = (T)((double)ldnt(AZ + j * ld + i) + taq);
-                stnt(Q + j * ld + i, qn);
-                stnt(AQ + j * ld + i, aqn);
-                q[j] = (double)qn;
-                aq[j] = (double)aqn;
+                const T zj = kPreload ? zv[j] : ldnt(Z + j * ld + i);
+                const T azj = kPreload ? azv[j] : ldnt(AZ + j * ld + i);
+                qn[j] = (T)((double)zj + tq);
+                aqn[j] = (T)((double)azj + taq);
+                q[j] = (double)qn[j];
+                aq[j] = (double)aqn[j];
+                if constexpr (!kPreload) {
+                    stnt(Q + j * ld + i, qn[j]);
+                    stnt(AQ + j * ld + i, aqn[j]);
+                }
+            }
+            if constexpr (kPreload) {
+#pragma unroll
+                for (int j = 0; j < S; ++j) {
+                    stnt(Q + j * ld + i, qn[j]);
+                    stnt(AQ + j * ld + i, aqn[j]);
+                }
+            }
+            if constexpr (MODE == 2) {
+                // a select, not a branch, so the load of x stays with the
+                // others; without a pending update x is written back as read
+                double qa = 0.0;
+#pragma unroll
+                for (int j = 0; j < S; ++j) qa = fma(qo[j], al[j], qa);
+                stnt(x + i, pend ? (T)((double)xi + qa) : xi);
             }
         }
-        const double ri = (double)ldnt(r + i);
+        const double ri = (double)(kPreload ? rv : ldnt(r + i));
         int e = 0;
 #pragma unroll
         for (int a = 0; a < S; ++a)
@@ -168,6 +223,8 @@ __global__ __launch_bounds__(kRowBlock) void k_gram_rect(int64_t n, int64_t ld,
 
 // R consecutive rows per thread as R-wide vectors (R = 16 bytes / element
 // when every column is 16-byte aligned), each row computed as with R = 1.
+// x == nullptr: r, z1 and ||r||^2 only (the solve defers x += Q alpha to the
+// next block update).
 template <int S, typename T, int R>
 __global__ __launch_bounds__(kRowBlock) void k_xr(int64_t n, int64_t ld, const T* __restrict__ Q,
                                                   const T* __restrict__ AQ,
@@ -191,27 +248,33 @@ __global__ __launch_bounds__(kRowBlock) void k_xr(int64_t n, int64_t ld, const T
         if constexpr (R > 1) {
             if (i + R <= n) {
                 typedef T VT __attribute__((ext_vector_type(R)));
-                double qa[R], aqa[R];
+                double aqa[R];
 #pragma unroll
-                for (int e = 0; e < R; ++e) qa[e] = aqa[e] = 0.0;
+                for (int e = 0; e < R; ++e) aqa[e] = 0.0;
 #pragma unroll
                 for (int j = 0; j < S; ++j) {
-                    const VT q = ldnt(reinterpret_cast<const VT*>(Q + j * ld + i));
                     const VT aq = ldnt(reinterpret_cast<const VT*>(AQ + j * ld + i));
 #pragma unroll
-                    for (int e = 0; e < R; ++e) {
-                        qa[e] = fma((double)q[e], al[j], qa[e]);
-                        aqa[e] = fma((double)aq[e], al[j], aqa[e]);
-                    }
+                    for (int e = 0; e < R; ++e) aqa[e] = fma((double)aq[e], al[j], aqa[e]);
                 }
-                VT xv = *reinterpret_cast<const VT*>(x + i);
+                if (x) {
+                    double qa[R];
+#pragma unroll
+                    for (int e = 0; e < R; ++e) qa[e] = 0.0;
+#pragma unroll
+                    for (int j = 0; j < S; ++j) {
+                        const VT q = ldnt(reinterpret_cast<const VT*>(Q + j * ld + i));
+#pragma unroll
+                        for (int e = 0; e < R; ++e) qa[e] = fma((double)q[e], al[j], qa[e]);
+                    }
+                    VT xv = *reinterpret_cast<const VT*>(x + i);
+#pragma unroll
+                    for (int e = 0; e < R; ++e) xv[e] = (T)((double)xv[e] + qa[e]);
+                    *reinterpret_cast<VT*>(x + i) = xv;
+                }
                 VT rv = *reinterpret_cast<const VT*>(r + i);
 #pragma unroll
-                for (int e = 0; e < R; ++e) {
-                    xv[e] = (T)((double)xv[e] + qa[e]);
-                    rv[e] = (T)((double)rv[e] - aqa[e]);
-                }
-                *reinterpret_cast<VT*>(x + i) = xv;
+                for (int e = 0; e < R; ++e) rv[e] = (T)((double)rv[e] - aqa[e]);
                 *reinterpret_cast<VT*>(r + i) = rv;
                 if (z1) {
                     const VT dv = ldnt(reinterpret_cast<const VT*>(dinv + i));
@@ -227,13 +290,15 @@ __global__ __launch_bounds__(kRowBlock) void k_xr(int64_t n, int64_t ld, const T
         }
         for (int e = 0; e < R && i + e < n; ++e) {
             const int64_t k = i + e;
-            double qa = 0.0, aqa = 0.0;
+            double aqa = 0.0;
 #pragma unroll
-            for (int j = 0; j < S; ++j) {
-                qa = fma((double)ldnt(Q + j * ld + k), al[j], qa);
-                aqa = fma((double)ldnt(AQ + j * ld + k), al[j], aqa);
+            for (int j = 0; j < S; ++j) aqa = fma((double)ldnt(AQ + j * ld + k), al[j], aqa);
+            if (x) {
+                double qa = 0.0;
+#pragma unroll
+                for (int j = 0; j < S; ++j) qa = fma((double)ldnt(Q + j * ld + k), al[j], qa);
+                x[k] = (T)((double)x[k] + qa);
             }
-            x[k] = (T)((double)x[k] + qa);
             const T rk = (T)((double)r[k] - aqa);
             r[k] = rk;
             if (z1) stnt(z1 + k, (T)((double)ldnt(dinv + k) * (double)rk));
@@ -252,6 +317,24 @@ __global__ __launch_bounds__(kRowBlock) void k_axpy_up(int64_t n, double* __rest
     const int64_t stride = (int64_t)gridDim.x * kRowBlock;
     for (int64_t i = (int64_t)blockIdx.x * kRowBlock + threadIdx.x; i < n; i += stride)
         x[i] += (double)d[i];
+}
+
+// x += Q alpha if the solve ended with that update still pending (the
+// arithmetic of k_xr, row by row).
+template <typename T>
+__global__ __launch_bounds__(kRowBlock) void k_x_pending(int64_t n, int s, int64_t ld,
+                                                         const T* __restrict__ Q,
+                                                         const double* __restrict__ alpha,
+                                                         T* __restrict__ x,
+                                                         const Ctrl* __restrict__ ctrl)
+{
+    if (!ctrl->x_pending) return;
+    const int64_t stride = (int64_t)gridDim.x * kRowBlock;
+    for (int64_t i = (int64_t)blockIdx.x * kRowBlock + threadIdx.x; i < n; i += stride) {
+        double qa = 0.0;
+        for (int j = 0; j < s; ++j) qa = fma((double)Q[j * ld + i], alpha[j], qa);
+        x[i] = (T)((double)x[i] + qa);
+    }
 }
 
 template <typename T>
@@ -282,22 +365,26 @@ static int block_grid(int64_t n, K kernel)
 
 template <typename T>
 int launch_update_gram(int64_t n, int s, const T* Z, T* Q, const T* AZ, T* AQ, const double* beta,
-                       const T* r, int64_t ld, double* partials, int* G_out, const Ctrl* ctrl,
-                       hipStream_t st)
+                       const T* r, T* x, const double* alpha, int64_t ld, double* partials,
+                       int* G_out, const Ctrl* ctrl, hipStream_t st)
 {
     int G = 0;
     switch (s) {
-#define X(S)                                                                                     \
-    case S:                                                                                      \
-        if (beta) {                                                                              \
-            G = block_grid(n, k_update_gram<S, T, false>);                                       \
-            hipLaunchKernelGGL((k_update_gram<S, T, false>), dim3(G), dim3(kRowBlock), 0, st, n, \
-                               ld, Z, Q, AZ, AQ, beta, r, partials, ctrl);                       \
-        } else {                                                                                 \
-            G = block_grid(n, k_update_gram<S, T, true>);                                        \
-            hipLaunchKernelGGL((k_update_gram<S, T, true>), dim3(G), dim3(kRowBlock), 0, st, n,  \
-                               ld, Z, Q, AZ, AQ, beta, r, partials, ctrl);                       \
-        }                                                                                        \
+#define X(S)                                                                                    \
+    case S:                                                                                     \
+        if (!beta) {                                                                            \
+            G = block_grid(n, k_update_gram<S, T, 0>);                                          \
+            hipLaunchKernelGGL((k_update_gram<S, T, 0>), dim3(G), dim3(kRowBlock), 0, st, n, ld, \
+                               Z, Q, AZ, AQ, beta, r, x, alpha, partials, ctrl);                \
+        } else if (!x || !ctrl) {                                                               \
+            G = block_grid(n, k_update_gram<S, T, 1>);                                          \
+            hipLaunchKernelGGL((k_update_gram<S, T, 1>), dim3(G), dim3(kRowBlock), 0, st, n, ld, \
+                               Z, Q, AZ, AQ, beta, r, x, alpha, partials, ctrl);                \
+        } else {                                                                                \
+            G = block_grid(n, k_update_gram<S, T, 2>);                                          \
+            hipLaunchKernelGGL((k_update_gram<S, T, 2>), dim3(G), dim3(kRowBlock), 0, st, n, ld, \
+                               Z, Q, AZ, AQ, beta, r, x, alpha, partials, ctrl);                \
+        }                                                                                       \
         break;
         SSPCG_S_CASES(X)
 #undef X
@@ -388,6 +475,16 @@ int launch_axpy_up(int64_t n, double* x, const T* d, const Ctrl* ctrl, hipStream
 }
 
 template <typename T>
+int launch_x_pending(int64_t n, int s, const T* Q, const double* alpha, int64_t ld, T* x,
+                     const Ctrl* ctrl, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_x_pending<T>), dim3(row_grid(n)), dim3(kRowBlock), 0, st, n, s, ld, Q,
+                       alpha, x, ctrl);
+    SSPCG_LAUNCHED("k_x_pending");
+    return SSPCG_OK;
+}
+
+template <typename T>
 int launch_fill(int64_t n, T* x, T v, hipStream_t st)
 {
     hipLaunchKernelGGL((k_fill<T>), dim3(row_grid(n)), dim3(kRowBlock), 0, st, n, x, v);
@@ -397,13 +494,15 @@ int launch_fill(int64_t n, T* x, T v, hipStream_t st)
 
 #define SSPCG_INST(T)                                                                            \
     template int launch_update_gram<T>(int64_t, int, const T*, T*, const T*, T*, const double*, \
-                                       const T*, int64_t, double*, int*, const Ctrl*,           \
-                                       hipStream_t);                                             \
+                                       const T*, T*, const double*, int64_t, double*, int*,     \
+                                       const Ctrl*, hipStream_t);                                \
     template int launch_gram_rect<T>(int64_t, int, const T*, const T*, int64_t, double*, int*,  \
                                      const Ctrl*, hipStream_t);                                  \
     template int launch_xr<T>(int64_t, int, const T*, const T*, const double*, int64_t, T*, T*, \
                               const T*, T*, double*, int*, const Ctrl*, hipStream_t);           \
     template int launch_axpy_up<T>(int64_t, double*, const T*, const Ctrl*, hipStream_t);       \
+    template int launch_x_pending<T>(int64_t, int, const T*, const double*, int64_t, T*,        \
+                                     const Ctrl*, hipStream_t);                                  \
     template int launch_fill<T>(int64_t, T*, T, hipStream_t);
 SSPCG_INST(double)
 SSPCG_INST(float)

@@ -32,7 +32,9 @@ struct Ctrl {
     double relres;      // last relative residual
     double rho[2];      // classical PCG: r^T z, double-buffered by iteration parity
     double sums[4];     // results of the setup reductions
-    double pad[5];
+    int32_t x_pending;  // 1 while x still lacks Q alpha of the last r update
+    int32_t pad_i;
+    double pad[4];
 };
 static_assert(sizeof(Ctrl) == 128, "Ctrl layout");
 

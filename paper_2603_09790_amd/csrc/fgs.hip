@@ -142,6 +142,9 @@ __global__ __launch_bounds__(kFinBlock) void k_fgs_step(int which, const double*
                                                         double* __restrict__ hist)
 {
     if (ctrl->done) return;
+    // the alpha system follows the block update, which has applied any
+    // pending x += Q alpha with the previous alpha before this overwrites it
+    if (which == 0 && threadIdx.x == 0) ctrl->x_pending = 0;
     const int K = which == 0 ? S * (S + 1) / 2 + S : S * S;
     __shared__ double sv[S * S + S];
     __shared__ double W[S][S], L[S][S], B[S][S], X[S][S];
@@ -248,6 +251,9 @@ __global__ __launch_bounds__(kWave) void k_norm_step(const double* __restrict__ 
     if (ctrl->done) return;
     const double rr = wave_finish(partials, 0, G);
     if (threadIdx.x != 0) return;
+    // the x/r update before this step changed r only: x += Q alpha is
+    // applied by the next block update (or at the end of the solve)
+    ctrl->x_pending = 1;
     const int64_t k = ctrl->iter;
     const double relres = sqrt(rr) / ctrl->nb;
     ctrl->relres = relres;

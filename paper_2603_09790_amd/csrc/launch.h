@@ -89,10 +89,12 @@ int launch_pcg_pupdate(int64_t n, int64_t k, const double* z, double* p, const d
 
 // Block kernels (block.hip).
 int row_grid(int64_t n);
+// beta == nullptr: the first update (Q = Z, AQ = AZ).  x != nullptr: also
+// x += Q alpha with the incoming Q when ctrl->x_pending is set.
 template <typename T>
 int launch_update_gram(int64_t n, int s, const T* Z, T* Q, const T* AZ, T* AQ,
-                       const double* beta, const T* r, int64_t ld, double* partials,
-                       int* G_out, const Ctrl* ctrl, hipStream_t st);
+                       const double* beta, const T* r, T* x, const double* alpha, int64_t ld,
+                       double* partials, int* G_out, const Ctrl* ctrl, hipStream_t st);
 template <typename T>
 int launch_gram_rect(int64_t n, int s, const T* Q, const T* AZ, int64_t ld, double* partials,
                      int* G_out, const Ctrl* ctrl, hipStream_t st);
@@ -102,6 +104,10 @@ int launch_xr(int64_t n, int s, const T* Q, const T* AQ, const double* alpha, in
               const Ctrl* ctrl, hipStream_t st);
 template <typename T>
 int launch_axpy_up(int64_t n, double* x, const T* d, const Ctrl* ctrl, hipStream_t st);
+// x += Q alpha if ctrl->x_pending (the end of a solve).
+template <typename T>
+int launch_x_pending(int64_t n, int s, const T* Q, const double* alpha, int64_t ld, T* x,
+                     const Ctrl* ctrl, hipStream_t st);
 template <typename T>
 int launch_fill(int64_t n, T* x, T v, hipStream_t st);
 

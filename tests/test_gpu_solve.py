@@ -407,8 +407,14 @@ def test_graph_replay_matches_eager(poisson5, check_every):
             torch.cuda.synchronize()
             assert ig["status"] == P.OK and ig["outer_iters"] == ie["outer_iters"]
             assert torch.equal(xg, xe) and torch.equal(xe2, xe)
-    # the iteration limit is respected in graph mode too
+    # the iteration limit is respected in graph mode too, and the iterate
+    # left there (with its last x update applied after the loop) is the
+    # eager solve's
     with torch.cuda.stream(s_):
         xl, il = P.solve(w["M"], b, s=4, sweeps=2, interval=w["interval"], tol=1e-10,
                          max_outer=13, check_every=8, graph=True)
+        xle, ile = P.solve(w["M"], b, s=4, sweeps=2, interval=w["interval"], tol=1e-10,
+                           max_outer=13, check_every=8)
+    torch.cuda.synchronize()
     assert il["status"] == P.NOT_CONVERGED and il["outer_iters"] == 13
+    assert ile["outer_iters"] == 13 and torch.equal(xl, xle)
