@@ -68,11 +68,13 @@ def csr_family_bytes(n: int, nnz: int, s: int, elem: int) -> float:
 
 
 def phase_bytes(n: int, s: int, elem: int) -> dict:
-    """Algorithmic bytes of the other phases per launch."""
+    """Algorithmic bytes of the other phases per launch, as the solve runs
+    them: its block update also applies the previous x += Q alpha (x read
+    and written), so its x/r update touches neither x nor Q."""
     return {
-        "gram_update": (6 * s + 1) * n * elem,   # read Z, Q, AZ, AQ, r; write Q, AQ
+        "gram_update": (6 * s + 3) * n * elem,   # read Z, Q, AZ, AQ, r, x; write Q, AQ, x
         "gram_rect": 2 * s * n * elem,           # read Q, AZ
-        "xr": (2 * s + 6) * n * elem,            # read x, Q, r, AQ, dinv; write x, r, z1
+        "xr": (s + 4) * n * elem,                # read AQ, r, dinv; write r, z1
     }
 
 
