@@ -74,15 +74,16 @@ struct Sell {
     int32_t uo[32];             // uniform: the global offset list, in the kernel arguments
     // LDS staging of x (uniform layout): the gathers x[row + o_k] of a
     // 256-row tile starting at row a fall into one window per run of
-    // consecutive offsets (o, o+1, ...): x[a + lo .. a + lo + w), w = 256 +
-    // the run's span.  Each workgroup copies its windows to LDS slots of
-    // lds_w elements with contiguous loads, then reads entry k of tile row t
-    // at sx[lds_k[k] + t].  lds_n = 0: gathers from memory (more than
-    // kMaxWindows runs, or the layout is not uniform).
+    // consecutive offsets (o, o+1, ...): x[a + lo .. a + lo + lds_w), lo the
+    // run's first offset rounded down to even, lds_w (even) >= 256 + the
+    // run's span + that rounding for every run.  Each workgroup copies its
+    // windows to LDS slots of lds_w elements with contiguous loads, then
+    // reads entry k of tile row t at sx[lds_k[k] + t].  lds_n = 0: gathers
+    // from memory (more than kMaxWindows runs, or the layout is not uniform).
     int32_t lds_n;              // staged elements per tile (ncl * lds_w)
-    int32_t ncl, lds_w;         // runs (windows), LDS slot length (the longest window)
+    int32_t ncl, lds_w;         // runs (windows), LDS slot length
     int32_t lds_self;           // LDS index of x[row] for tile row 0 (the offset 0)
-    int32_t cl_lo[32], cl_w[32];   // first offset and length of each window
+    int32_t cl_lo[32];          // first offset of each window (even)
     int32_t lds_k[32];          // LDS index of entry k for tile row 0 (stored pads: any window)
     int64_t nslices;
     const int64_t* slice_ptr;   // nslices + 1 slot offsets, multiples of 64

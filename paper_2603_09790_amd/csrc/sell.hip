@@ -475,33 +475,67 @@ __device__ inline double uniform_row(const Sell<T>& A, int64_t c, int lane, cons
 // ---- uniform layout with x staged in LDS (Sell::lds_n > 0)
 
 // Copies the tile's windows of x to LDS (all threads of the workgroup; the
-// caller synchronizes).  Thread t loads element t of every window, and the
-// few elements past 256 of each, into registers before it stores any, so
-// all loads are in flight together.  Elements outside [0, n) are staged as
-// 0: the entries that would read them are stored zeros.
+// caller synchronizes).  Windows start at even offsets and all have the even
+// length lds_w, and tiles start at multiples of 256 rows, so every window is
+// a run of element pairs 16-byte aligned in x (when x is) and in LDS: each
+// thread moves a pair per load.  Half of the workgroup copies window 2m and
+// the other half window 2m + 1 (elements 0..255); one more load per thread
+// covers the few elements past 256 of every window.  All loads are issued
+// before the first store.  Elements outside [0, n) are staged as 0: the
+// entries that would read them are stored zeros.
 template <typename T>
 __device__ inline void stage_x(const Sell<T>& A, int64_t a, const T* __restrict__ x,
                                T* __restrict__ sx)
 {
+    typedef T T2 __attribute__((ext_vector_type(2)));
+    constexpr int kHalf = kRowBlock / 2;
+    constexpr int kRounds = (kMaxWindows + 1) / 2;
     const int t = threadIdx.x;
-    T head[kMaxWindows], tail[kMaxWindows];
-#pragma unroll
-    for (int j = 0; j < kMaxWindows; ++j) {
-        head[j] = tail[j] = (T)0;
-        if (j < A.ncl) {
-            const int64_t g = a + A.cl_lo[j] + t;
-            if (g >= 0 && g < A.n) head[j] = x[g];
-            const int64_t g2 = g + kRowBlock;
-            if (kRowBlock + t < A.cl_w[j] && g2 >= 0 && g2 < A.n) tail[j] = x[g2];
+    // the half is the same for all lanes of a wave: keep it (and the window
+    // index) scalar, so the window offsets are scalar loads of the kernel
+    // arguments rather than vector loads that stall the staging
+    const int half = __builtin_amdgcn_readfirstlane(t) / kHalf, u = t % kHalf;
+    const bool x16 = reinterpret_cast<uintptr_t>(x) % (2 * sizeof(T)) == 0;
+    auto load2 = [&](int64_t g) {
+        T2 v;
+        if (x16 && g >= 0 && g + 1 < A.n) {
+            v = *reinterpret_cast<const T2*>(x + g);
+        } else {
+            v.x = (g >= 0 && g < A.n) ? x[g] : (T)0;
+            v.y = (g + 1 >= 0 && g + 1 < A.n) ? x[g + 1] : (T)0;
         }
+        return v;
+    };
+    T2 head[kRounds];
+#pragma unroll
+    for (int m = 0; m < kRounds; ++m) {
+        const int j = 2 * m + half;
+        head[m] = (T2)((T)0);
+        if (j < A.ncl) head[m] = load2(a + A.cl_lo[j] + 2 * u);
+    }
+    // pairs kHalf .. lds_w/2 - 1 of the windows, one per thread (the plan
+    // keeps ncl * tp <= 256)
+    const int tp = A.lds_w / 2 - kHalf;
+    const bool has_tail = t < A.ncl * tp;
+    int tj = 0, tq = 0;
+    T2 tail = (T2)((T)0);
+    if (has_tail) {
+        tj = t / tp;
+        tq = t - tj * tp;
+        // per-lane window: select among the scalar offsets (a select of the
+        // loads themselves would become one vector load at a selected address)
+        int lo = __builtin_amdgcn_readfirstlane(A.cl_lo[0]);
+#pragma unroll
+        for (int j = 1; j < kMaxWindows; ++j)
+            lo = tj == j ? __builtin_amdgcn_readfirstlane(A.cl_lo[j]) : lo;
+        tail = load2(a + lo + kRowBlock + 2 * tq);
     }
 #pragma unroll
-    for (int j = 0; j < kMaxWindows; ++j) {
-        if (j < A.ncl) {
-            sx[j * A.lds_w + t] = head[j];
-            if (kRowBlock + t < A.cl_w[j]) sx[j * A.lds_w + kRowBlock + t] = tail[j];
-        }
+    for (int m = 0; m < kRounds; ++m) {
+        const int j = 2 * m + half;
+        if (j < A.ncl) *reinterpret_cast<T2*>(sx + j * A.lds_w + 2 * u) = head[m];
     }
+    if (has_tail) *reinterpret_cast<T2*>(sx + tj * A.lds_w + kRowBlock + 2 * tq) = tail;
 }
 
 // Full storage, x from LDS: entry k of tile row t multiplies sx[lds_k[k] + t]
@@ -638,7 +672,7 @@ __global__ __launch_bounds__(kRowBlock) void k_spmv(Sell<T> A, const T* __restri
     bool staged = false;
     if constexpr (sizeof(T) == 8) staged = A.lds_n > 0;   // FP32 views never stage
     if (staged) {
-        extern __shared__ double lds_dyn[];
+        extern __shared__ __attribute__((aligned(16))) double lds_dyn[];
         T* sx = reinterpret_cast<T*>(lds_dyn);
         stage_x<T>(A, tile * kRowBlock, x, sx);
         __syncthreads();
@@ -682,7 +716,7 @@ __global__ __launch_bounds__(kRowBlock) void k_residual(Sell<double> A, const do
     const int64_t ntiles = (A.nslices + kSlicesPerTile - 1) / kSlicesPerTile;
     const TileRange tr = xcd_tiles(ntiles);
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    extern __shared__ double lds_dyn[];
+    extern __shared__ __attribute__((aligned(16))) double lds_dyn[];
     for (int64_t t = tr.first; t < tr.end; t += tr.step) {
         const int64_t c = t * kSlicesPerTile + wave;
         double ax = 0.0;
@@ -728,7 +762,7 @@ __global__ __launch_bounds__(kRowBlock) void k_pcg_spmv(Sell<double> A, const do
     const int64_t ntiles = (A.nslices + kSlicesPerTile - 1) / kSlicesPerTile;
     const TileRange tr = xcd_tiles(ntiles);
     double acc[1] = {0.0};
-    extern __shared__ double lds_dyn[];
+    extern __shared__ __attribute__((aligned(16))) double lds_dyn[];
     for (int64_t t = tr.first; t < tr.end; t += tr.step) {
         const int64_t c = t * kSlicesPerTile + wave;
         double ap = 0.0;
@@ -894,22 +928,24 @@ void plan_lds(sspcg_matrix* A)
     if (!A->uniform || A->uw < 1) return;
     const int32_t* o = A->uoff_host;
     int j = -1;
-    int run[kMaxUnion];
+    int run[kMaxUnion], last[kMaxUnion];
     for (int k = 0; k < A->uw; ++k) {
-        if (k == 0 || o[k] != o[k - 1] + 1) {
-            ++j;
-            A->cl_lo[j] = o[k];
-            A->cl_w[j] = kRowBlock;
-        } else {
-            ++A->cl_w[j];
-        }
+        if (k == 0 || o[k] != o[k - 1] + 1) A->cl_lo[++j] = o[k];
+        last[j] = o[k];
         run[k] = j;
     }
     const int ncl = j + 1;
     if (ncl > kMaxWindows) return;   // too many windows: gathers from memory
+    // windows start at even offsets (rounded down) and share an even length,
+    // so they are staged as aligned pairs of elements
     int w = 0;
-    for (int r = 0; r < ncl; ++r) w = std::max(w, A->cl_w[r]);
+    for (int r = 0; r < ncl; ++r) {
+        A->cl_lo[r] &= ~1;
+        w = std::max(w, kRowBlock + last[r] - A->cl_lo[r]);
+    }
+    w += w & 1;
     if (w > 2 * kRowBlock) return;   // a run longer than the tile: not worth staging
+    if (ncl * (w / 2 - kRowBlock / 2) > kRowBlock) return;   // tails: one pair per thread
     for (int k = 0; k < A->uw; ++k) A->lds_k[k] = run[k] * w + (o[k] - A->cl_lo[run[k]]);
     for (int k = A->uw; k < kMaxUnion; ++k) A->lds_k[k] = A->lds_k[A->uw - 1];
     // the element x[row] itself, for the epilogue of the matrix powers kernel
@@ -956,7 +992,6 @@ static Sell<T> make_view(const sspcg_matrix* A, int uwv, const T* val, const T* 
     S.lds_w = A->lds_w;
     S.lds_self = A->lds_self;
     std::copy(A->cl_lo, A->cl_lo + kMaxUnion, S.cl_lo);
-    std::copy(A->cl_w, A->cl_w + kMaxUnion, S.cl_w);
     std::copy(A->lds_k, A->lds_k + kMaxUnion, S.lds_k);
     S.nslices = A->nslices;
     S.slice_ptr = A->slice_ptr;
