@@ -201,6 +201,27 @@ def test_iteration_limit(poisson5):
     assert rel(x, xo) <= 1e-12
 
 
+@pytest.mark.parametrize("shift,s", [(0.5, 2), (0.5, 4), (1.0, 2)])
+def test_breakdown_returns_last_iterate(shift, s):
+    """A symmetric indefinite matrix (positive diagonal): the Gram solve
+    breaks down after a few outer iterations, as in the oracle, and x is the
+    oracle's last iterate there (including the x update that the solve
+    defers to the next block update)."""
+    A = si.poisson5(16)
+    d = A.col == np.repeat(np.arange(A.n), np.diff(A.row_ptr))
+    val = A.val.copy()
+    val[d] -= shift
+    B = si.CSR(A.n, A.row_ptr, A.col, val, A.shape3)
+    b = si.rhs_uniform(A.n)
+    xo, ro = oracle.sspcg(B, b, s=s, sweeps=2, interval=(0.05, 8.0), tol=1e-10, max_outer=200)
+    assert ro["status"] == oracle.BREAKDOWN and ro["iters"] >= 1
+    M = P.Matrix.from_csr(B, device=DEV)
+    x, info = P.solve(M, gpu(b), s=s, sweeps=2, interval=(0.05, 8.0), tol=1e-10, max_outer=200,
+                      raise_on_error=False)
+    assert info["status"] == P.ERR_BREAKDOWN and info["outer_iters"] == ro["iters"]
+    assert rel(x.cpu().numpy(), xo) <= 1e-10
+
+
 @pytest.mark.parametrize("kind,N,s", [("5pt", 3, 2), ("5pt", 9, 16), ("7pt", 5, 3),
                                       ("27pt", 4, 5)])
 def test_small_and_ragged_systems(kind, N, s):
