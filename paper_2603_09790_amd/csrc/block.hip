@@ -2,12 +2,15 @@
 // block update + Gram reduction, the right-hand side of the beta system,
 // and the x / r update with the residual norm and the first basis vector.
 //
-// All are row-parallel and stream every input once: thread i owns row i of
-// every column (columns are ld apart, so a wave's load of one column is 512
-// contiguous bytes).  Gram sums are FP64 per thread, then reduced over the
-// block in a fixed order into per-block partials; a single-block kernel
-// finishes them (fgs.hip).  The step size s is a template parameter so the
-// s(s+1)/2 + s accumulators live in registers.
+// All are row-parallel and stream every input once: a thread owns one row
+// (or R consecutive rows, read as 16-byte vectors) of every column (columns
+// are ld apart, so a wave's load of one column is contiguous).  Gram sums are
+// FP64 per thread, then reduced over the block in a fixed order into
+// per-block partials; a single-block kernel finishes them (fgs.hip).  The
+// step size s is a template parameter so the s(s+1)/2 + s accumulators live
+// in registers.  In the solve, x += Q alpha of an outer iteration is applied
+// by the next block update, which reads that Q anyway (k_update_gram MODE 2),
+// or after the loop (k_x_pending).
 
 #include "launch.h"
 
