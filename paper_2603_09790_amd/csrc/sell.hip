@@ -401,20 +401,24 @@ __device__ inline double row_uniform_half(const Sell<T>& A, int64_t c, int lane,
     constexpr int V = HalfV<T>::value;
     typedef T VT __attribute__((ext_vector_type(V)));
     const int64_t row = c * kSlice + lane;
-    const int32_t self = (int32_t)(row < A.n ? row : A.n - 1);
-    const uint32_t m = A.smask[row];
     const int h = H > 0 ? H : A.uw / 2;
     const int uw = H > 0 ? 2 * H + 1 : A.uw;
     const int nv = NV > 0 ? NV : A.uwv / V;
     const int64_t sw = NV > 0 ? (int64_t)kSlice * NV * V : (int64_t)kSlice * A.uwv;
+    // an absent neighbour holds a stored zero, so the gather index only has
+    // to stay inside x: clamped, with no mask to load first
+    const int32_t last = A.n - 1;
+    auto gather = [&](int k) {
+        const int32_t i = (int32_t)row + A.uo[k];
+        return (double)x[i < 0 ? 0 : (i > last ? last : i)];
+    };
     double acc = 0.0;
     auto lower = [&](int k) {
         const int64_t r = row + A.uo[k];
         const int64_t rc = r < 0 ? 0 : r;
         const int t = h - k;
         const T v = A.val[(rc >> 6) * sw + (int64_t)(t / V) * (kSlice * V) + (rc & 63) * V + t % V];
-        const int32_t idx = (m >> k) & 1u ? (int32_t)row + A.uo[k] : self;
-        acc = fma(r < 0 ? 0.0 : (double)v, (double)x[idx], acc);
+        acc = fma(r < 0 ? 0.0 : (double)v, gather(k), acc);
     };
     const VT* vp = reinterpret_cast<const VT*>(A.val + c * sw) + lane;
     auto upper = [&](int j) {
@@ -422,10 +426,7 @@ __device__ inline double row_uniform_half(const Sell<T>& A, int64_t c, int lane,
 #pragma unroll
         for (int e = 0; e < V; ++e) {
             const int k = h + j * V + e;
-            if (k < uw) {
-                const int32_t idx = (m >> k) & 1u ? (int32_t)row + A.uo[k] : self;
-                acc = fma((double)v[e], (double)x[idx], acc);
-            }
+            if (k < uw) acc = fma((double)v[e], gather(k), acc);
         }
     };
     if constexpr (H > 0) {
