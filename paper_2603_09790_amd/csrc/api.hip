@@ -815,7 +815,7 @@ int sspcg_matrix_create(int32_t n, int32_t nnz, const int32_t* row_ptr, const in
     A->nshared = plan.nshared;
     if (A->slots >= ((int64_t)1 << 40)) return fail_union(arg_error("matrix too large"));
     if (!plan.uoff.empty()) {
-        // uniform layout: offsets, masks and vector-grouped values only
+        // uniform layout: offsets and vector-grouped values only
         A->uniform = 1;
         A->uw = (int32_t)plan.uoff.size();
         A->usym = plan.usym ? 1 : 0;
@@ -823,18 +823,16 @@ int sspcg_matrix_create(int32_t n, int32_t nnz, const int32_t* row_ptr, const in
         A->slots = A->nslices * kSlice * stored;
         const int64_t rows = A->nslices * kSlice;
         const size_t b_uoff = 256;
-        const size_t b_mask = align_up(sizeof(uint32_t) * (size_t)rows, 256);
         const size_t b_val = align_up(sizeof(double) * (size_t)rows * ((stored + 1) / 2 * 2), 256);
         const int64_t stored32 = A->usym ? stored : (stored + 3) / 4 * 4;   // FP32 half: no grouping
         const size_t b_val32 = f32 ? align_up(sizeof(float) * (size_t)rows * stored32, 256) : 0;
-        e = hipMalloc(&A->mem_vals, b_uoff + b_mask + b_val + b_val32);
+        e = hipMalloc(&A->mem_vals, b_uoff + b_val + b_val32);
         if (e != hipSuccess) return fail_union(hip_fail(e, "hipMalloc(matrix values)"));
         char* mv = static_cast<char*>(A->mem_vals);
         A->uoff = reinterpret_cast<int32_t*>(mv);
-        A->smask = reinterpret_cast<uint32_t*>(mv + b_uoff);
-        A->sval = reinterpret_cast<double*>(mv + b_uoff + b_mask);
-        A->sval32 = f32 ? reinterpret_cast<float*>(mv + b_uoff + b_mask + b_val) : nullptr;
-        A->mem_bytes = b_small + b_uoff + b_mask + b_val + b_val32;
+        A->sval = reinterpret_cast<double*>(mv + b_uoff);
+        A->sval32 = f32 ? reinterpret_cast<float*>(mv + b_uoff + b_val) : nullptr;
+        A->mem_bytes = b_small + b_uoff + b_val + b_val32;
         std::copy(plan.uoff.begin(), plan.uoff.end(), A->uoff_host);
         plan_lds(A);
         e = hipMemcpyAsync(A->uoff, plan.uoff.data(), sizeof(int32_t) * plan.uoff.size(),
@@ -850,18 +848,16 @@ int sspcg_matrix_create(int32_t n, int32_t nnz, const int32_t* row_ptr, const in
     }
     const size_t b_col = align_up(sizeof(int32_t) * (size_t)plan.ncol, 256);
     const size_t b_off = align_up(sizeof(int32_t) * (size_t)plan.nsoff, 256);
-    const size_t b_mask = plan.nshared ? align_up(sizeof(uint32_t) * (size_t)A->nslices * kSlice, 256) : 0;
     const size_t b_val = align_up(sizeof(double) * (size_t)A->slots, 256);
     const size_t b_val32 = f32 ? align_up(sizeof(float) * (size_t)A->slots, 256) : 0;
-    e = hipMalloc(&A->mem_vals, b_col + b_off + b_mask + b_val + b_val32);
+    e = hipMalloc(&A->mem_vals, b_col + b_off + b_val + b_val32);
     if (e != hipSuccess) return fail_union(hip_fail(e, "hipMalloc(matrix values)"));
     char* mv = static_cast<char*>(A->mem_vals);
     A->scol = reinterpret_cast<int32_t*>(mv);
     A->soff = reinterpret_cast<int32_t*>(mv + b_col);
-    A->smask = plan.nshared ? reinterpret_cast<uint32_t*>(mv + b_col + b_off) : nullptr;
-    A->sval = reinterpret_cast<double*>(mv + b_col + b_off + b_mask);
-    A->sval32 = f32 ? reinterpret_cast<float*>(mv + b_col + b_off + b_mask + b_val) : nullptr;
-    A->mem_bytes = b_small + b_col + b_off + b_mask + b_val + b_val32;
+    A->sval = reinterpret_cast<double*>(mv + b_col + b_off);
+    A->sval32 = f32 ? reinterpret_cast<float*>(mv + b_col + b_off + b_val) : nullptr;
+    A->mem_bytes = b_small + b_col + b_off + b_val + b_val32;
     e = hipMemcpyAsync(A->slice_ptr, plan.slice_ptr.data(), sizeof(int64_t) * plan.slice_ptr.size(),
                        hipMemcpyHostToDevice, st);
     if (e == hipSuccess)

@@ -44,9 +44,9 @@ static_assert(sizeof(Ctrl) == 128, "Ctrl layout");
 //  - shared offsets (slice_aux[c] < 0): the slice's rows draw their columns
 //    from one sorted list of at most 32 offsets o_k = col - row, stored once
 //    at soff[-slice_aux[c] - 1 + k]; entry k of a row is its value at column
-//    row + o_k, or 0 where the row has no such entry, and bit k of the row's
-//    mask smask[row] says whether it has one.  This is the case for stencil
-//    matrices and removes the column indices from the stream.
+//    row + o_k, or 0 where the row has no such entry (its gather then reads
+//    any element of x: an exact zero term for finite x).  This is the case
+//    for stencil matrices and removes the column indices from the stream.
 //  - explicit columns (slice_aux[c] >= 0): entry k holds the row's k-th
 //    stored entry, its column at col[slice_aux[c] + 64k + l]; rows are padded
 //    to the slice's longest row with value 0 and the row as column.
@@ -90,12 +90,12 @@ struct Sell {
     const int64_t* slice_aux;   // kind and offset of each slice, see above
     const int32_t* col;         // explicit column indices
     const int32_t* soff;        // shared offset lists
-    const uint32_t* smask;      // per row (nslices * 64): entries present at the offsets
     const T* val;
     const T* dinv;              // 1 / diag(A)
 };
 
-// Longest shared offset list a slice may use (the width of a row mask).
+// Longest shared offset list a slice may use (the offsets travel in kernel
+// arguments for the uniform layout).
 constexpr int kMaxUnion = 32;
 constexpr int kMaxWindows = 12;    // LDS windows of x per tile at most (about 27 KB in FP64)
 static_assert(sizeof(Sell<double>::uo) == kMaxUnion * sizeof(int32_t), "offset list size");

@@ -14,7 +14,6 @@ struct sspcg_matrix {
     int64_t* slice_aux = nullptr;       // owned (inside `mem`)
     int32_t* scol = nullptr;            // owned (inside `mem_vals`)
     int32_t* soff = nullptr;            // owned (inside `mem_vals`)
-    uint32_t* smask = nullptr;          // owned (inside `mem_vals`)
     int32_t uniform = 0, uw = 0;        // uniform layout: global offset list length
     int32_t usym = 0;                   // uniform layout: symmetric half storage
     int32_t* uoff = nullptr;            // owned (inside `mem_vals`)
@@ -27,7 +26,7 @@ struct sspcg_matrix {
     float* dinv32 = nullptr;
     int32_t* dflags = nullptr;
     void* mem = nullptr;                // device allocation: slice_ptr/aux, dinv, dinv32, dflags
-    void* mem_vals = nullptr;           // device allocation: scol, soff, smask, sval, sval32
+    void* mem_vals = nullptr;           // device allocation: scol, soff, sval, sval32
     size_t mem_bytes = 0;
     sspcg::Ctrl* host_ctrl = nullptr;   // pinned mirror for polling (2 entries)
     sspcg_profile profile{};            // last profiled solve

@@ -153,7 +153,6 @@ __global__ __launch_bounds__(kRowBlock) void k_fill(int32_t n, int64_t nslices,
                                                     const int64_t* __restrict__ slice_aux,
                                                     const int32_t* __restrict__ soff,
                                                     int32_t* __restrict__ scol,
-                                                    uint32_t* __restrict__ smask,
                                                     double* __restrict__ sval,
                                                     float* __restrict__ sval32, bool values_only)
 {
@@ -171,19 +170,16 @@ __global__ __launch_bounds__(kRowBlock) void k_fill(int32_t n, int64_t nslices,
     if (aux < 0) {
         const int32_t* off = soff + (-aux - 1);
         int32_t p = 0;
-        uint32_t mask = 0;
         for (int k = 0; k < w; ++k) {
             double v = 0.0;
             if (p < len && col[a + p] - (int32_t)i == off[k]) {
                 v = val[a + p];
-                mask |= 1u << k;
                 ++p;
             }
             const int64_t slot = base + (int64_t)k * kSlice + lane;
             sval[slot] = v;
             if (sval32) sval32[slot] = (float)v;
         }
-        if (!values_only) smask[i] = mask;
     } else {
         for (int k = 0; k < w; ++k) {
             const int64_t slot = base + (int64_t)k * kSlice + lane;
@@ -241,10 +237,8 @@ __global__ __launch_bounds__(kRowBlock) void k_fill_uniform(int32_t n, int64_t n
                                                             const double* __restrict__ val,
                                                             const int32_t* __restrict__ uoff, int uw,
                                                             int h0, int uwv64, int uwv32, int v32,
-                                                            uint32_t* __restrict__ smask,
                                                             double* __restrict__ sval,
-                                                            float* __restrict__ sval32,
-                                                            bool values_only)
+                                                            float* __restrict__ sval32)
 {
     const int64_t i = (int64_t)blockIdx.x * kRowBlock + threadIdx.x;
     const int64_t c = i / kSlice;
@@ -256,13 +250,11 @@ __global__ __launch_bounds__(kRowBlock) void k_fill_uniform(int32_t n, int64_t n
         len = rp[i + 1] - a;
     }
     double v[kMaxUnion];
-    uint32_t mask = 0;
     int32_t p = 0;
     for (int k = 0; k < uw; ++k) {
         v[k] = 0.0;
         if (p < len && col[a + p] - (int32_t)i == uoff[k]) {
             v[k] = val[a + p];
-            mask |= 1u << k;
             ++p;
         }
     }
@@ -271,7 +263,6 @@ __global__ __launch_bounds__(kRowBlock) void k_fill_uniform(int32_t n, int64_t n
     if (sval32)
         for (int t = 0; t < uwv32; ++t)
             sval32[uslot(c, t, lane, uwv32, v32)] = h0 + t < uw ? (float)v[h0 + t] : 0.0f;
-    if (!values_only) smask[i] = mask;
 }
 
 // ------------------------------------------------------------------ SpMV
@@ -310,14 +301,20 @@ __device__ inline double row_explicit(const int32_t* __restrict__ cp, const T* _
     return acc;
 }
 
-// Sum of one row of a shared-offset slice: entry k multiplies x[row + o_k],
-// or x[self] (with the stored zero: an exact zero term) where bit k of the
-// row's mask is clear.  The gather addresses depend only on the mask and the
-// offsets, so values and gathers are in flight together.
+// Gather index of entry k of a row: row + o_k clamped into [0, last].  A row
+// without an entry at o_k holds a stored zero there, so whatever element the
+// clamped index reaches adds an exact zero term (x finite); no mask has to be
+// loaded first, and values and gathers are in flight together.
+__device__ inline int32_t gather_index(int32_t row, int32_t o, int32_t last)
+{
+    const int64_t i = (int64_t)row + o;
+    return (int32_t)(i < 0 ? 0 : (i > last ? last : i));
+}
+
+// Sum of one row of a shared-offset slice: entry k multiplies x[row + o_k].
 template <typename T, int U>
 __device__ inline double row_shared(const int32_t* __restrict__ off, const T* __restrict__ vp, int w,
-                                    uint32_t mask, int32_t row, int32_t self,
-                                    const T* __restrict__ x)
+                                    int32_t row, int32_t last, const T* __restrict__ x)
 {
     double acc = 0.0;
     int k = 0;
@@ -326,13 +323,13 @@ __device__ inline double row_shared(const int32_t* __restrict__ off, const T* __
 #pragma unroll
         for (int u = 0; u < U; ++u) vv[u] = ld_stream(vp + (int64_t)(k + u) * kSlice);
 #pragma unroll
-        for (int u = 0; u < U; ++u) xx[u] = x[(mask >> (k + u)) & 1u ? row + off[k + u] : self];
+        for (int u = 0; u < U; ++u) xx[u] = x[gather_index(row, off[k + u], last)];
 #pragma unroll
         for (int u = 0; u < U; ++u) acc = fma((double)vv[u], (double)xx[u], acc);
     }
     for (; k < w; ++k) {
         const T vv = ld_stream(vp + (int64_t)k * kSlice);
-        acc = fma((double)vv, (double)x[(mask >> k) & 1u ? row + off[k] : self], acc);
+        acc = fma((double)vv, (double)x[gather_index(row, off[k], last)], acc);
     }
     return acc;
 }
@@ -351,8 +348,9 @@ struct Vec16<float> {
 };
 
 // Row of the uniform layout: NV 16-byte vectors per lane (NV > 0: known at
-// compile time, fully unrolled; NV = 0: runtime count).  The gather index
-// depends only on the mask and the offsets, so all loads are independent.
+// compile time, fully unrolled; NV = 0: runtime count).  The gather indices
+// depend only on the row and the offsets, so all loads are independent
+// (padding entries past the list hold zeros and gather a valid element).
 template <typename T, int NV>
 __device__ inline double row_uniform(const Sell<T>& A, int64_t c, int lane,
                                      const T* __restrict__ x)
@@ -360,8 +358,6 @@ __device__ inline double row_uniform(const Sell<T>& A, int64_t c, int lane,
     constexpr int V = 16 / sizeof(T);
     typedef typename Vec16<T>::type VT;
     const int64_t row = c * kSlice + lane;
-    const int32_t self = (int32_t)(row < A.n ? row : A.n - 1);
-    const uint32_t m = A.smask[row];
     const VT* vp = reinterpret_cast<const VT*>(A.val + c * kSlice * A.uwv) + lane;
     const int nv = NV > 0 ? NV : A.uwv / V;
     double acc = 0.0;
@@ -371,8 +367,7 @@ __device__ inline double row_uniform(const Sell<T>& A, int64_t c, int lane,
 #pragma unroll
         for (int h = 0; h < V; ++h) {
             const int k = j * V + h;
-            const int32_t idx = (m >> k) & 1u ? (int32_t)row + A.uo[k] : self;
-            acc = fma((double)v[h], (double)x[idx], acc);
+            acc = fma((double)v[h], (double)x[gather_index((int32_t)row, A.uo[k], A.n - 1)], acc);
         }
     }
     return acc;
@@ -405,13 +400,7 @@ __device__ inline double row_uniform_half(const Sell<T>& A, int64_t c, int lane,
     const int uw = H > 0 ? 2 * H + 1 : A.uw;
     const int nv = NV > 0 ? NV : A.uwv / V;
     const int64_t sw = NV > 0 ? (int64_t)kSlice * NV * V : (int64_t)kSlice * A.uwv;
-    // an absent neighbour holds a stored zero, so the gather index only has
-    // to stay inside x: clamped, with no mask to load first
-    const int32_t last = A.n - 1;
-    auto gather = [&](int k) {
-        const int32_t i = (int32_t)row + A.uo[k];
-        return (double)x[i < 0 ? 0 : (i > last ? last : i)];
-    };
+    auto gather = [&](int k) { return (double)x[gather_index((int32_t)row, A.uo[k], A.n - 1)]; };
     double acc = 0.0;
     auto lower = [&](int k) {
         const int64_t r = row + A.uo[k];
@@ -646,11 +635,9 @@ __device__ inline double slice_row(const Sell<T>& A, int64_t c, int lane, const 
     const int64_t base = A.slice_ptr[c], aux = A.slice_aux[c];
     const int w = (int)((A.slice_ptr[c + 1] - base) / kSlice);
     const int64_t row = c * kSlice + lane;
-    if (aux < 0) {
-        const int32_t self = (int32_t)(row < A.n ? row : A.n - 1);
-        return row_shared<T, kUnroll>(A.soff + (-aux - 1), A.val + base + lane, w, A.smask[row],
-                                      (int32_t)row, self, x);
-    }
+    if (aux < 0)
+        return row_shared<T, kUnroll>(A.soff + (-aux - 1), A.val + base + lane, w, (int32_t)row,
+                                      A.n - 1, x);
     return row_explicit<T, kUnroll>(A.col + aux + lane, A.val + base + lane, w, x);
 }
 
@@ -999,7 +986,6 @@ static Sell<T> make_view(const sspcg_matrix* A, int uwv, const T* val, const T* 
     S.slice_aux = A->slice_aux;
     S.col = A->scol;
     S.soff = A->soff;
-    S.smask = A->smask;
     S.val = val;
     S.dinv = dinv;
     return S;
@@ -1176,15 +1162,14 @@ int matrix_fill(sspcg_matrix* A, const double* val, bool values_only, hipStream_
         hipLaunchKernelGGL(k_fill_uniform, dim3(blocks), dim3(kRowBlock), 0, st, A->n, A->nslices,
                            A->row_ptr, A->col, val, A->uoff, A->uw, A->uw - stored,
                            sell_view<double>(A).uwv, sell_view<float>(A).uwv,
-                           A->usym ? HalfV<float>::value : 4, A->smask, A->sval, A->sval32,
-                           values_only);
+                           A->usym ? HalfV<float>::value : 4, A->sval, A->sval32);
         SSPCG_LAUNCHED("k_fill_uniform");
         SSPCG_HIP(hipStreamSynchronize(st));
         return SSPCG_OK;
     }
     hipLaunchKernelGGL(k_fill, dim3(blocks), dim3(kRowBlock), 0, st, A->n, A->nslices, A->row_ptr,
-                       A->col, val, A->slice_ptr, A->slice_aux, A->soff, A->scol, A->smask,
-                       A->sval, A->sval32, values_only);
+                       A->col, val, A->slice_ptr, A->slice_aux, A->soff, A->scol, A->sval,
+                       A->sval32, values_only);
     SSPCG_LAUNCHED("k_fill");
     SSPCG_HIP(hipStreamSynchronize(st));
     return SSPCG_OK;
