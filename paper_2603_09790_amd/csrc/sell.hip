@@ -692,7 +692,9 @@ __global__ __launch_bounds__(kRowBlock) void k_spmv(Sell<T> A, const T* __restri
     }
 }
 
-template <typename TR>
+// STAGED: the uniform layout with x staged in LDS (A.lds_n > 0), the only
+// row code the kernel then holds, so the persistent loop keeps few registers.
+template <typename TR, bool STAGED>
 __global__ __launch_bounds__(kRowBlock) void k_residual(Sell<double> A, const double* __restrict__ x,
                                                         const double* __restrict__ b,
                                                         TR* __restrict__ r, TR* __restrict__ z1,
@@ -708,7 +710,7 @@ __global__ __launch_bounds__(kRowBlock) void k_residual(Sell<double> A, const do
     for (int64_t t = tr.first; t < tr.end; t += tr.step) {
         const int64_t c = t * kSlicesPerTile + wave;
         double ax = 0.0;
-        if (A.lds_n > 0) {
+        if constexpr (STAGED) {
             // every wave of the workgroup reaches both barriers of every tile
             __syncthreads();
             stage_x<double>(A, t * kRowBlock, x, lds_dyn);
@@ -739,6 +741,7 @@ __global__ __launch_bounds__(kRowBlock) void k_residual(Sell<double> A, const do
     block_partials<4, kRowBlock>(acc, partials);
 }
 
+template <bool STAGED>
 __global__ __launch_bounds__(kRowBlock) void k_pcg_spmv(Sell<double> A, const double* __restrict__ p,
                                                         double* __restrict__ q,
                                                         double* __restrict__ partials,
@@ -753,8 +756,8 @@ __global__ __launch_bounds__(kRowBlock) void k_pcg_spmv(Sell<double> A, const do
     extern __shared__ __attribute__((aligned(16))) double lds_dyn[];
     for (int64_t t = tr.first; t < tr.end; t += tr.step) {
         const int64_t c = t * kSlicesPerTile + wave;
-        double ap = 0.0;
-        if (A.lds_n > 0) {
+        double ap = 0.0, prow = 0.0;
+        if constexpr (STAGED) {
             // every wave of the workgroup reaches both barriers of every tile
             __syncthreads();
             stage_x<double>(A, t * kRowBlock, p, lds_dyn);
@@ -762,14 +765,16 @@ __global__ __launch_bounds__(kRowBlock) void k_pcg_spmv(Sell<double> A, const do
             if (c >= A.nslices) continue;
             double dg;
             ap = uniform_row_lds<double>(A, c, lane, (int)threadIdx.x, lds_dyn, dg);
+            prow = lds_dyn[A.lds_self + threadIdx.x];   // p[row], staged with offset 0
         } else {
             if (c >= A.nslices) break;
             ap = slice_row<double>(A, c, lane, p);
         }
         const int64_t row = c * kSlice + lane;
         if (row < A.n) {
+            if constexpr (!STAGED) prow = p[row];
             q[row] = ap;
-            acc[0] = fma(p[row], ap, acc[0]);
+            acc[0] = fma(prow, ap, acc[0]);
         }
     }
     block_partials<1, kRowBlock>(acc, partials);
@@ -1221,9 +1226,16 @@ int launch_residual(const sspcg_matrix* A, const double* x, const double* b, TR*
     const Sell<double> S = sell_view<double>(A);
     const TR* dinvT = sell_view<TR>(A).dinv;
     const size_t lds = lds_bytes<double>(A);
-    const int G = spmv_reduce_grid(A, k_residual<TR>, lds);
-    hipLaunchKernelGGL((k_residual<TR>), dim3(G), dim3(kRowBlock), lds, st, S, x, b, r, z1, dinvT,
-                       partials);
+    int G;
+    if (S.lds_n > 0) {
+        G = spmv_reduce_grid(A, k_residual<TR, true>, lds);
+        hipLaunchKernelGGL((k_residual<TR, true>), dim3(G), dim3(kRowBlock), lds, st, S, x, b, r,
+                           z1, dinvT, partials);
+    } else {
+        G = spmv_reduce_grid(A, k_residual<TR, false>, lds);
+        hipLaunchKernelGGL((k_residual<TR, false>), dim3(G), dim3(kRowBlock), lds, st, S, x, b, r,
+                           z1, dinvT, partials);
+    }
     SSPCG_LAUNCHED("k_residual");
     *G_out = G;
     return SSPCG_OK;
@@ -1237,10 +1249,18 @@ template int launch_residual<float>(const sspcg_matrix*, const double*, const do
 int launch_pcg_spmv(const sspcg_matrix* A, const double* p, double* q, double* partials,
                     int* G_out, const Ctrl* ctrl, hipStream_t st)
 {
+    const Sell<double> S = sell_view<double>(A);
     const size_t lds = lds_bytes<double>(A);
-    const int G = spmv_reduce_grid(A, k_pcg_spmv, lds);
-    hipLaunchKernelGGL(k_pcg_spmv, dim3(G), dim3(kRowBlock), lds, st, sell_view<double>(A), p, q,
-                       partials, ctrl);
+    int G;
+    if (S.lds_n > 0) {
+        G = spmv_reduce_grid(A, k_pcg_spmv<true>, lds);
+        hipLaunchKernelGGL((k_pcg_spmv<true>), dim3(G), dim3(kRowBlock), lds, st, S, p, q, partials,
+                           ctrl);
+    } else {
+        G = spmv_reduce_grid(A, k_pcg_spmv<false>, lds);
+        hipLaunchKernelGGL((k_pcg_spmv<false>), dim3(G), dim3(kRowBlock), lds, st, S, p, q,
+                           partials, ctrl);
+    }
     SSPCG_LAUNCHED("k_pcg_spmv");
     *G_out = G;
     return SSPCG_OK;
