@@ -9,15 +9,15 @@
 // col - row; such a slice stores its sorted offset list once and no column
 // indices at all (8 instead of 12 bytes per FP64 entry, 4 instead of 8 in
 // FP32), and the gathers x[row + o_k] of a wave are contiguous too.  A row
-// without an entry at offset o_k holds an exact zero there and gathers its
-// own element instead.  Slices whose offset union is too long keep explicit
-// columns (64 indices per entry k), padded to the longest row.  When one
-// list fits all slices the matrix uses the uniform layout instead (one
-// global list, 16-byte value groups, optionally one triangle of a
-// symmetric matrix, and in FP64 the gathered parts of x staged in LDS; see
-// Sell in common.h).  In every kind the entries of a row keep their CSR
-// order, which is the summation order, and a zero adds nothing (for finite
-// x): the sum is the CSR sum.
+// without an entry at offset o_k holds an exact zero there, and its gather
+// index is clamped into x.  Slices whose offset union is too long keep
+// explicit columns (64 indices per entry k), padded to the longest row.
+// When one list fits all slices the matrix uses the uniform layout instead
+// (one global list, 16-byte value groups, optionally one triangle of a
+// symmetric matrix, and in FP64 the gathered parts of x staged in LDS as
+// aligned element pairs; see Sell in common.h).  In every kind the entries
+// of a row keep their CSR order, which is the summation order, and a zero
+// adds nothing (for finite x): the sum is the CSR sum.
 
 #include <algorithm>
 #include <climits>
@@ -529,8 +529,8 @@ __device__ inline void stage_x(const Sell<T>& A, int64_t a, const T* __restrict_
 }
 
 // Full storage, x from LDS: entry k of tile row t multiplies sx[lds_k[k] + t]
-// (a row without that neighbour holds a stored zero there, so no mask is
-// needed; the stored padding entries point at a valid element too).
+// (a row without that neighbour holds a stored zero there; the stored
+// padding entries point at a valid element too).
 template <typename T, int NV>
 __device__ inline double row_uniform_lds(const Sell<T>& A, int64_t c, int lane, int t,
                                          const T* __restrict__ sx)
@@ -1105,7 +1105,7 @@ int matrix_inspect(sspcg_matrix* A, const double* val, bool values_only, LayoutP
     }
     plan->slots = plan->slice_ptr[A->nslices];
     // uniform layout: every slice shared, and the union of all their lists
-    // fits one mask and costs at most 2 % more stored entries than the
+    // has at most 32 offsets and costs at most 2 % more stored entries than the
     // per-slice lists -- or A is symmetric and one triangle of the union
     // needs fewer entries than the per-slice lists
     plan->uoff.clear();
