@@ -823,7 +823,8 @@ int sspcg_matrix_create(int32_t n, int32_t nnz, const int32_t* row_ptr, const in
         A->slots = A->nslices * kSlice * stored;
         const int64_t rows = A->nslices * kSlice;
         const size_t b_uoff = 256;
-        const size_t b_val = align_up(sizeof(double) * (size_t)rows * ((stored + 1) / 2 * 2), 256);
+        const int64_t stored64 = A->usym ? stored : (stored + 1) / 2 * 2;   // FP64 half: no grouping
+        const size_t b_val = align_up(sizeof(double) * (size_t)rows * stored64, 256);
         const int64_t stored32 = A->usym ? stored : (stored + 3) / 4 * 4;   // FP32 half: no grouping
         const size_t b_val32 = f32 ? align_up(sizeof(float) * (size_t)rows * stored32, 256) : 0;
         e = hipMalloc(&A->mem_vals, b_uoff + b_val + b_val32);

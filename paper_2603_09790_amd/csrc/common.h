@@ -63,8 +63,8 @@ static_assert(sizeof(Ctrl) == 128, "Ctrl layout");
 // its list is o_k = -o_{uw-1-k} (uw odd, o_{uw/2} = 0), only the entries
 // k >= h = uw/2 are stored, as t = k - h.  Entry k < h of row i is then
 // entry t = h - k of row i + o_k (zero when that row is below 0), which
-// halves the value stream.  FP64 keeps pairs (V = 2); FP32 stores single
-// values (V = 1), so uwv is the stored count itself.
+// halves the value stream.  Both precisions store single values (V = 1),
+// so uwv is the stored count itself.
 template <typename T>
 struct Sell {
     int32_t n;

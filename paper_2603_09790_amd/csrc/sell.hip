@@ -225,7 +225,8 @@ __global__ __launch_bounds__(kRowBlock) void k_check_symmetric(int32_t n,
 
 // Uniform layout: one thread per row walks its sorted columns against the
 // global offset list; stored entry t = k - h0 (h0 = 0, or uw/2 for the
-// symmetric half storage) in FP64 (pairs) and FP32 (quads).
+// symmetric half storage) in groups of v64 FP64 and v32 FP32 values (16
+// bytes each, or single values with the symmetric half storage).
 __device__ inline int64_t uslot(int64_t c, int k, int lane, int uwv, int V)
 {
     return c * kSlice * uwv + (int64_t)(k / V) * (kSlice * V) + lane * V + k % V;
@@ -236,7 +237,8 @@ __global__ __launch_bounds__(kRowBlock) void k_fill_uniform(int32_t n, int64_t n
                                                             const int32_t* __restrict__ col,
                                                             const double* __restrict__ val,
                                                             const int32_t* __restrict__ uoff, int uw,
-                                                            int h0, int uwv64, int uwv32, int v32,
+                                                            int h0, int uwv64, int v64, int uwv32,
+                                                            int v32,
                                                             double* __restrict__ sval,
                                                             float* __restrict__ sval32)
 {
@@ -259,7 +261,7 @@ __global__ __launch_bounds__(kRowBlock) void k_fill_uniform(int32_t n, int64_t n
         }
     }
     for (int t = 0; t < uwv64; ++t)
-        sval[uslot(c, t, lane, uwv64, 2)] = h0 + t < uw ? v[h0 + t] : 0.0;
+        sval[uslot(c, t, lane, uwv64, v64)] = h0 + t < uw ? v[h0 + t] : 0.0;
     if (sval32)
         for (int t = 0; t < uwv32; ++t)
             sval32[uslot(c, t, lane, uwv32, v32)] = h0 + t < uw ? (float)v[h0 + t] : 0.0f;
@@ -373,13 +375,16 @@ __device__ inline double row_uniform(const Sell<T>& A, int64_t c, int lane,
     return acc;
 }
 
-// Values per lane vector of the symmetric half storage: FP64 pairs, FP32
-// single values (the reads for negative offsets come from other rows, one
-// value per lane; with FP32 quads they would touch four times the cache
-// lines).
+// Values per lane vector of the symmetric half storage: single values in
+// both precisions.  The reads for negative offsets take one value per lane
+// from another row; grouped values would make each of them touch two (FP64
+// pairs) or four (FP32 quads) times the cache lines.  Measured at 192^3:
+// FP32 112 us single vs 160 us quads; FP64 with x staged in LDS 202 us
+// single vs 209 us pairs, although single values need 14 instead of 7 loads
+// for the row's own entries.
 template <typename T>
 struct HalfV {
-    static constexpr int value = sizeof(T) == 8 ? 2 : 1;
+    static constexpr int value = 1;
 };
 
 // Row of the symmetric half storage.  Entries k < H (negative offsets) are
@@ -436,20 +441,11 @@ __device__ inline double uniform_row(const Sell<T>& A, int64_t c, int lane, cons
     constexpr int V = 16 / sizeof(T);
     if (A.usym) {
         // (list length, stored vectors per row) of the 27-, 7- and 5-point stencils
-        if constexpr (sizeof(T) == 8) {
-            switch (A.uw * 32 + A.uwv / 2) {
-            case 27 * 32 + 7: return row_uniform_half<T, 13, 7>(A, c, lane, x);
-            case 7 * 32 + 2: return row_uniform_half<T, 3, 2>(A, c, lane, x);
-            case 5 * 32 + 2: return row_uniform_half<T, 2, 2>(A, c, lane, x);
-            default: return row_uniform_half<T, 0, 0>(A, c, lane, x);
-            }
-        } else {
-            switch (A.uw * 32 + A.uwv) {
-            case 27 * 32 + 14: return row_uniform_half<T, 13, 14>(A, c, lane, x);
-            case 7 * 32 + 4: return row_uniform_half<T, 3, 4>(A, c, lane, x);
-            case 5 * 32 + 3: return row_uniform_half<T, 2, 3>(A, c, lane, x);
-            default: return row_uniform_half<T, 0, 0>(A, c, lane, x);
-            }
+        switch (A.uw * 32 + A.uwv) {
+        case 27 * 32 + 14: return row_uniform_half<T, 13, 14>(A, c, lane, x);
+        case 7 * 32 + 4: return row_uniform_half<T, 3, 4>(A, c, lane, x);
+        case 5 * 32 + 3: return row_uniform_half<T, 2, 3>(A, c, lane, x);
+        default: return row_uniform_half<T, 0, 0>(A, c, lane, x);
         }
     }
     switch (A.uwv / V) {
@@ -601,20 +597,11 @@ __device__ inline double uniform_row_lds(const Sell<T>& A, int64_t c, int lane, 
 {
     constexpr int V = 16 / sizeof(T);
     if (A.usym) {
-        if constexpr (sizeof(T) == 8) {
-            switch (A.uw * 32 + A.uwv / 2) {
-            case 27 * 32 + 7: return row_uniform_half_lds<T, 13, 7>(A, c, lane, t, sx, dg);
-            case 7 * 32 + 2: return row_uniform_half_lds<T, 3, 2>(A, c, lane, t, sx, dg);
-            case 5 * 32 + 2: return row_uniform_half_lds<T, 2, 2>(A, c, lane, t, sx, dg);
-            default: return row_uniform_half_lds<T, 0, 0>(A, c, lane, t, sx, dg);
-            }
-        } else {
-            switch (A.uw * 32 + A.uwv) {
-            case 27 * 32 + 14: return row_uniform_half_lds<T, 13, 14>(A, c, lane, t, sx, dg);
-            case 7 * 32 + 4: return row_uniform_half_lds<T, 3, 4>(A, c, lane, t, sx, dg);
-            case 5 * 32 + 3: return row_uniform_half_lds<T, 2, 3>(A, c, lane, t, sx, dg);
-            default: return row_uniform_half_lds<T, 0, 0>(A, c, lane, t, sx, dg);
-            }
+        switch (A.uw * 32 + A.uwv) {
+        case 27 * 32 + 14: return row_uniform_half_lds<T, 13, 14>(A, c, lane, t, sx, dg);
+        case 7 * 32 + 4: return row_uniform_half_lds<T, 3, 4>(A, c, lane, t, sx, dg);
+        case 5 * 32 + 3: return row_uniform_half_lds<T, 2, 3>(A, c, lane, t, sx, dg);
+        default: return row_uniform_half_lds<T, 0, 0>(A, c, lane, t, sx, dg);
         }
     }
     switch (A.uwv / V) {
@@ -999,7 +986,8 @@ static Sell<T> make_view(const sspcg_matrix* A, int uwv, const T* val, const T* 
 template <>
 Sell<double> sell_view<double>(const sspcg_matrix* A)
 {
-    return make_view<double>(A, (uniform_stored(A) + 1) / 2 * 2, A->sval, A->dinv);
+    return make_view<double>(A, A->usym ? uniform_stored(A) : (uniform_stored(A) + 1) / 2 * 2,
+                             A->sval, A->dinv);
 }
 
 template <>
@@ -1136,7 +1124,7 @@ int matrix_inspect(sspcg_matrix* A, const double* val, bool values_only, LayoutP
             // symmetric half storage: a list o_k = -o_{uw-1-k} and A = A^T
             bool mirrored = uw % 2 == 1;
             for (int k = 0; k < uw && mirrored; ++k) mirrored = all[k] == -all[uw - 1 - k];
-            const int half = (uw - uw / 2 + 1) / 2 * 2;   // stored FP64 entries per row
+            const int half = uw - uw / 2;   // stored entries per row
             if (allow_sym && mirrored && rows * half <= (double)plan->slots) {
                 bool sym = false;
                 const int rc = matrix_check_symmetric(A, val, &sym, st);
@@ -1166,8 +1154,9 @@ int matrix_fill(sspcg_matrix* A, const double* val, bool values_only, hipStream_
         const int stored = uniform_stored(A);
         hipLaunchKernelGGL(k_fill_uniform, dim3(blocks), dim3(kRowBlock), 0, st, A->n, A->nslices,
                            A->row_ptr, A->col, val, A->uoff, A->uw, A->uw - stored,
-                           sell_view<double>(A).uwv, sell_view<float>(A).uwv,
-                           A->usym ? HalfV<float>::value : 4, A->sval, A->sval32);
+                           sell_view<double>(A).uwv, A->usym ? HalfV<double>::value : 2,
+                           sell_view<float>(A).uwv, A->usym ? HalfV<float>::value : 4, A->sval,
+                           A->sval32);
         SSPCG_LAUNCHED("k_fill_uniform");
         SSPCG_HIP(hipStreamSynchronize(st));
         return SSPCG_OK;
