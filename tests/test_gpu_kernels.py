@@ -106,6 +106,18 @@ def test_spmv_fp32_bit_exact(sys_):
     assert np.array_equal(y, ref)
 
 
+def test_spmv_unaligned_x_same_result(sys_):
+    """x not 16-byte aligned: the LDS staging falls back to single-element
+    loads (and the gathers are unaffected); the product is the same bits."""
+    A, _, _, M = sys_
+    x = np.random.default_rng(7).normal(size=A.n)
+    buf = torch.zeros(A.n + 1, dtype=torch.float64, device=DEV)
+    buf[1:] = gpu(x)
+    xu = buf[1:]
+    assert xu.data_ptr() % 16 == 8
+    assert torch.equal(P.spmv(M, xu), P.spmv(M, gpu(x)))
+
+
 def test_matrix_info_and_padding(sys_):
     A, _, _, M = sys_
     info = M.info()
