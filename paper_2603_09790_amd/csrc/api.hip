@@ -1110,8 +1110,7 @@ int sspcg_block_update_gram(int64_t n, int32_t s, int32_t dtype, const void* Z, 
                                              static_cast<double*>(Q), static_cast<const double*>(AZ),
                                              static_cast<double*>(AQ), beta,
                                              static_cast<const double*>(r), nullptr, nullptr, ld,
-                                             part, &G, nullptr,
-                                             st));
+                                             part, &G, nullptr, st));
     return launch_gram_out(s, 0, part, G, W, b1, st);
     API_CATCH
 }
