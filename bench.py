@@ -463,7 +463,15 @@ def other_configs(P, torch, dev, args):
         loss.backward()
         torch.cuda.synchronize()
         t2 = time.time()
+    # the two solves inside: forward A x = b, adjoint A lambda = x - x_target
+    # (the matrix holds A(theta) from the step above)
+    _, i_f = P.solve(M, b, **opts)
+    _, i_b = P.solve(M, (x.detach() - xt).contiguous(), **opts)
     out["diffusion7_96_grad"] = {"forward_s": t1 - t0, "backward_s": t2 - t1,
+                                 "forward_solve": {"outer_iters": i_f["outer_iters"],
+                                                   "device_ms": i_f["device_ms"]},
+                                 "adjoint_solve": {"outer_iters": i_b["outer_iters"],
+                                                   "device_ms": i_b["device_ms"]},
                                  "loss": loss.item(),
                                  "grad_norm": torch.linalg.vector_norm(theta.grad).item()}
     log(f"[configs] diffusion7 96^3 gradient: {out['diffusion7_96_grad']}")
