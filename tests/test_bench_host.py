@@ -1,0 +1,70 @@
+"""Host logic of bench.py (no GPU): the one-GPU guard, the byte models the
+roofline divides by, and the guard on the counter-traffic record."""
+import hashlib
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+import bench
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
+
+
+def test_csr_model_matches_the_per_unit_figure():
+    # 27-point 192^3: 12 B per nonzero, 4 B per row pointer, 8 B per vector
+    # element read or written; one SpMV moves x and y
+    n, nnz = 7077888, 189119224
+    one = 12 * nnz + 4 * (n + 1) + 16 * n
+    assert abs(one - 2.4105e9) < 1e6
+    # the s launches of a matrix powers kernel add the epilogues: dinv read
+    # and z_{q+1} written for q < s, z_{q-1} read for 2 <= q < s
+    s = 6
+    epi = 8 * n * (2 + 3 * (s - 2))
+    assert bench.csr_family_bytes(n, nnz, s, 8) == s * one + epi
+
+
+def test_stored_format_model():
+    n, nnz, s = 1000, 26000, 4
+    nval = bench.stored_values(n, nnz, True)
+    assert nval == (nnz + n) // 2 and bench.stored_values(n, nnz, False) == nnz
+    # uniform layout: no column indices; the half storage reads no dinv
+    one = 8 * nval + 16 * n
+    assert bench.spmv_bytes(n, nval, 8, 0.0) == one
+    assert bench.spmv_bytes(n, nval, 8, 1.0) == one + 4 * nval
+    with_dinv = bench.spmv_family_bytes(n, nval, s, 8, 0.0)
+    without = bench.spmv_family_bytes(n, nval, s, 8, 0.0, dinv_read=False)
+    assert with_dinv - without == 8 * n * (s - 1)
+    assert without == s * one + 8 * n * (1 + 2 * (s - 2))
+
+
+def test_phase_bytes_follow_the_solve_kernels():
+    n, s = 100, 6
+    pb = bench.phase_bytes(n, s, 8)
+    assert pb["gram_update"] == (6 * s + 3) * 8 * n   # Z, Q, AZ, AQ, r, x in; Q, AQ, x out
+    assert pb["gram_rect"] == 2 * s * 8 * n           # Q, AZ
+    assert pb["xr"] == (s + 4) * 8 * n                # AQ, r, dinv in; r, z1 out
+
+
+def test_traffic_record_is_ignored_when_the_sources_change(tmp_path, monkeypatch):
+    src = tmp_path / "kernel.hip"
+    src.write_text("// kernel v1\n")
+    rec = {"sources": [str(src)], "source_sha256": hashlib.sha256(b"// kernel v1\n").hexdigest(),
+           "traffic_bytes_per_launch": 123.0}
+    path = tmp_path / "record.json"
+    path.write_text(json.dumps(rec))
+    monkeypatch.setattr(bench, "TRAFFIC_RECORD", str(path))
+    assert bench.counter_traffic() == 123.0
+    src.write_text("// kernel v2\n")
+    assert bench.counter_traffic() is None
+    path.write_text("not json")
+    assert bench.counter_traffic() is None
