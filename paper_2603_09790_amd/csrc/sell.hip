@@ -375,54 +375,37 @@ __device__ inline double row_uniform(const Sell<T>& A, int64_t c, int lane,
     return acc;
 }
 
-// Values per lane vector of the symmetric half storage: single values in
-// both precisions.  The reads for negative offsets take one value per lane
-// from another row; grouped values would make each of them touch two (FP64
-// pairs) or four (FP32 quads) times the cache lines.  Measured at 192^3:
-// FP32 112 us single vs 160 us quads; FP64 with x staged in LDS 202 us
-// single vs 209 us pairs, although single values need 14 instead of 7 loads
-// for the row's own entries.
-template <typename T>
-struct HalfV {
-    static constexpr int value = 1;
-};
-
-// Row of the symmetric half storage.  Entries k < H (negative offsets) are
-// read from row r = row + o_k, stored entry H - k (an exact zero when r < 0;
-// rows past the boundary otherwise hold the stored zero of the missing pair),
-// entries k >= H from the row's own NV vectors; the sum runs in list order
-// like the full layout's.  These loads are cached: the value a row reads for
-// a negative offset was streamed by row r shortly before.  H, NV > 0: known
-// at compile time; 0: from the matrix.
+// Row of the symmetric half storage (single values per lane in both
+// precisions: stored entry t of slice row l at slice base + 64t + l).
+// Entries k < H (negative offsets) are read from row r = row + o_k, stored
+// entry H - k (an exact zero when r < 0; rows past the boundary otherwise
+// hold the stored zero of the missing pair), entries k >= H are the row's own
+// NV = H + 1 stored entries; the sum runs in list order like the full
+// layout's.  These loads are cached: the value a row reads for a negative
+// offset was streamed by row r shortly before.  Grouping a lane's values in
+// 16-byte vectors would make every such read touch two (FP64) or four (FP32)
+// times the cache lines it uses; measured at 192^3: FP32 112 us single vs
+// 160 us quads, FP64 with x staged in LDS 202 us single vs 209 us pairs,
+// although single values take 14 instead of 7 loads for the own entries.
+// H, NV > 0: known at compile time; 0: from the matrix.
 template <typename T, int H, int NV>
 __device__ inline double row_uniform_half(const Sell<T>& A, int64_t c, int lane,
                                           const T* __restrict__ x)
 {
-    constexpr int V = HalfV<T>::value;
-    typedef T VT __attribute__((ext_vector_type(V)));
     const int64_t row = c * kSlice + lane;
     const int h = H > 0 ? H : A.uw / 2;
-    const int uw = H > 0 ? 2 * H + 1 : A.uw;
-    const int nv = NV > 0 ? NV : A.uwv / V;
-    const int64_t sw = NV > 0 ? (int64_t)kSlice * NV * V : (int64_t)kSlice * A.uwv;
+    const int nv = NV > 0 ? NV : A.uwv;
+    const int64_t sw = (int64_t)kSlice * nv;
     auto gather = [&](int k) { return (double)x[gather_index((int32_t)row, A.uo[k], A.n - 1)]; };
     double acc = 0.0;
     auto lower = [&](int k) {
         const int64_t r = row + A.uo[k];
         const int64_t rc = r < 0 ? 0 : r;
-        const int t = h - k;
-        const T v = A.val[(rc >> 6) * sw + (int64_t)(t / V) * (kSlice * V) + (rc & 63) * V + t % V];
+        const T v = A.val[(rc >> 6) * sw + (int64_t)(h - k) * kSlice + (rc & 63)];
         acc = fma(r < 0 ? 0.0 : (double)v, gather(k), acc);
     };
-    const VT* vp = reinterpret_cast<const VT*>(A.val + c * sw) + lane;
-    auto upper = [&](int j) {
-        const VT v = vp[(int64_t)j * kSlice];
-#pragma unroll
-        for (int e = 0; e < V; ++e) {
-            const int k = h + j * V + e;
-            if (k < uw) acc = fma((double)v[e], gather(k), acc);
-        }
-    };
+    const T* vp = A.val + c * sw + lane;
+    auto upper = [&](int j) { acc = fma((double)vp[(int64_t)j * kSlice], gather(h + j), acc); };
     if constexpr (H > 0) {
 #pragma unroll
         for (int k = 0; k < H; ++k) lower(k);
@@ -552,30 +535,22 @@ template <typename T, int H, int NV>
 __device__ inline double row_uniform_half_lds(const Sell<T>& A, int64_t c, int lane, int t,
                                               const T* __restrict__ sx, T& dg)
 {
-    constexpr int V = HalfV<T>::value;
-    typedef T VT __attribute__((ext_vector_type(V)));
     const int64_t row = c * kSlice + lane;
     const int h = H > 0 ? H : A.uw / 2;
-    const int uw = H > 0 ? 2 * H + 1 : A.uw;
-    const int nv = NV > 0 ? NV : A.uwv / V;
-    const int64_t sw = NV > 0 ? (int64_t)kSlice * NV * V : (int64_t)kSlice * A.uwv;
+    const int nv = NV > 0 ? NV : A.uwv;
+    const int64_t sw = (int64_t)kSlice * nv;
     double acc = 0.0;
     auto lower = [&](int k) {
         const int64_t r = row + A.uo[k];
         const int64_t rc = r < 0 ? 0 : r;
-        const int tt = h - k;
-        const T v = A.val[(rc >> 6) * sw + (int64_t)(tt / V) * (kSlice * V) + (rc & 63) * V + tt % V];
+        const T v = A.val[(rc >> 6) * sw + (int64_t)(h - k) * kSlice + (rc & 63)];
         acc = fma(r < 0 ? 0.0 : (double)v, (double)sx[A.lds_k[k] + t], acc);
     };
-    const VT* vp = reinterpret_cast<const VT*>(A.val + c * sw) + lane;
+    const T* vp = A.val + c * sw + lane;
     auto upper = [&](int j) {
-        const VT v = vp[(int64_t)j * kSlice];
-        if (j == 0) dg = v[0];
-#pragma unroll
-        for (int e = 0; e < V; ++e) {
-            const int k = h + j * V + e;
-            if (k < uw) acc = fma((double)v[e], (double)sx[A.lds_k[k] + t], acc);
-        }
+        const T v = vp[(int64_t)j * kSlice];
+        if (j == 0) dg = v;
+        acc = fma((double)v, (double)sx[A.lds_k[h + j] + t], acc);
     };
     if constexpr (H > 0) {
 #pragma unroll
@@ -1154,8 +1129,8 @@ int matrix_fill(sspcg_matrix* A, const double* val, bool values_only, hipStream_
         const int stored = uniform_stored(A);
         hipLaunchKernelGGL(k_fill_uniform, dim3(blocks), dim3(kRowBlock), 0, st, A->n, A->nslices,
                            A->row_ptr, A->col, val, A->uoff, A->uw, A->uw - stored,
-                           sell_view<double>(A).uwv, A->usym ? HalfV<double>::value : 2,
-                           sell_view<float>(A).uwv, A->usym ? HalfV<float>::value : 4, A->sval,
+                           sell_view<double>(A).uwv, A->usym ? 1 : 2, sell_view<float>(A).uwv,
+                           A->usym ? 1 : 4, A->sval,
                            A->sval32);
         SSPCG_LAUNCHED("k_fill_uniform");
         SSPCG_HIP(hipStreamSynchronize(st));
