@@ -14,6 +14,10 @@
  * - Pointers named in a "device" argument are HIP device addresses; all
  *   others are host addresses.  Device buffers are owned by the caller and
  *   must stay alive until the work that uses them has finished on `stream`.
+ * - The library allocates no memory on the device and no pinned host memory:
+ *   the matrix copy (`aux`), solver workspaces, kernel scratch and the
+ *   polling buffer of the solvers all come from the caller, sized by the
+ *   *_bytes query functions.
  * - `stream` is a hipStream_t passed as a plain pointer; NULL selects the
  *   default stream.  Kernel-level calls only enqueue work and return; the
  *   solve calls block until the solve has finished.
@@ -41,7 +45,7 @@
 extern "C" {
 #endif
 
-#define SSPCG_ABI_VERSION 2
+#define SSPCG_ABI_VERSION 3
 #define SSPCG_MAX_S 16          /* largest supported step size s */
 
 typedef void* sspcg_stream;     /* hipStream_t */
@@ -94,7 +98,7 @@ typedef struct {
     int32_t max_refine;         /* MIXED: limit on FP64 residual corrections */
     int32_t gram;               /* sspcg_gram_solver */
     int32_t check_every;        /* outer iterations enqueued between host polls (>= 1) */
-    int32_t profile;            /* 1: time every phase with HIP events (sspcg_last_profile) */
+    int32_t profile;            /* 1: time every phase with HIP events (profile output) */
     double sweep_tol;           /* 0: exactly `sweeps` FGS sweeps.  > 0: each right-hand side
                                    stops sweeping once ||m - W a|| <= sweep_tol ||m|| (the
                                    accuracy criterion of Sec. 3), after at most `sweeps` */
@@ -109,10 +113,19 @@ typedef struct {
     int32_t status;             /* sspcg_status */
     int32_t outer_iters;        /* x updates taken (FP64) / inner iterations summed (MIXED) */
     int32_t refinements;        /* MIXED: FP64 corrections applied */
-    int32_t reserved;
-    double relres;              /* ||r|| / ||b|| of the residual the stop test used */
+    int32_t inner_iters_total;  /* MIXED: inner outer-iterations summed over the refinements;
+                                   FP64 and PCG: equal to outer_iters */
+    double relres;              /* ||r|| / ||b|| of the residual the stop test used (the
+                                   recursive r in FP64 and PCG, the FP64 true r in MIXED) */
+    double relres_true;         /* ||b - A x|| / ||b|| of the returned x, recomputed in FP64
+                                   on the device after the solve (one more SpMV) */
     double device_ms;           /* GPU time of the solve, from HIP events */
 } sspcg_result;
+
+/* Host buffer the solvers poll the device through: pinned host memory
+ * (hipHostMalloc, or a torch tensor with pin_memory=True), at least this
+ * many bytes, 64-byte aligned.  One per concurrently running solve. */
+#define SSPCG_POLL_BYTES 256
 
 /* Phases of the s-step solve, as timed by the profile. */
 enum {
@@ -125,9 +138,9 @@ enum {
     SSPCG_NUM_PHASES
 };
 
-/* Per-phase GPU time of the last profiled solve on a matrix handle, counted
- * over the phases that did work (the launches enqueued after the stop test
- * passed, which return at once, are excluded). */
+/* Per-phase GPU time of a profiled solve, counted over the phases that did
+ * work (the launches enqueued after the stop test passed, which return at
+ * once, are excluded). */
 typedef struct {
     int64_t launches[SSPCG_NUM_PHASES];   /* kernel launches that did work */
     double ms[SSPCG_NUM_PHASES];          /* GPU time between the bracketing events */
@@ -144,14 +157,36 @@ const char* sspcg_last_error(void);
 void sspcg_default_params(sspcg_params* p);
 
 /* ---------------------------------------------------------------- matrix */
-/* Builds the library's copy of a CSR matrix on the current device.
+/* The library keeps its own layout of A (below) in a caller-provided device
+ * buffer `aux`.  Its size depends on the sparsity pattern, so it is found in
+ * two steps:
+ *   1. sspcg_matrix_scratch_bytes(n): device scratch for the analysis;
+ *   2. sspcg_matrix_aux_bytes(...): checks the CSR on the device, chooses
+ *      the layout, and returns the exact size of `aux`;
+ * then sspcg_matrix_create builds the layout in `aux`.  The scratch can be
+ * released once step 2 has returned. */
+size_t sspcg_matrix_scratch_bytes(int32_t n);
+
+/* CSR input of both calls below:
  *   row_ptr (device, int32[n+1]), col (device, int32[nnz]), val (device,
- *   double[nnz]): CSR with row_ptr[0] = 0, increasing row pointers, columns in
- *   [0, n) and every diagonal entry stored.  Column order inside a row fixes
- *   the summation order of the SpMV.
- * The library allocates device memory for its sliced layout, the Jacobi
- * scaling 1/diag(A) and, with SSPCG_MATRIX_FP32, FP32 copies of both; it
- * frees them in sspcg_matrix_destroy.  The call synchronizes `stream`.
+ *   double[nnz]): row_ptr[0] = 0, increasing row pointers, columns in [0, n)
+ *   and every diagonal entry stored.  Column order inside a row fixes the
+ *   summation order of the SpMV.
+ * scratch (device, >= sspcg_matrix_scratch_bytes(n), 256-byte aligned).
+ * aux_bytes (host, required): the device bytes sspcg_matrix_create needs in
+ * `aux` for this pattern, these values (whether A is symmetric bit for bit
+ * decides the layout) and these flags.  Synchronizes `stream`.
+ * Errors as for sspcg_matrix_create. */
+int sspcg_matrix_aux_bytes(int32_t n, int32_t nnz, const int32_t* row_ptr, const int32_t* col,
+                           const double* val, int32_t flags, void* scratch, size_t scratch_bytes,
+                           sspcg_stream stream, size_t* aux_bytes);
+
+/* Builds the library's copy of a CSR matrix (arguments as above) in `aux`
+ * (device, >= the aux_bytes reported for the same pattern, values and
+ * flags; 256-byte aligned; owned by the caller and kept alive, unmoved,
+ * until sspcg_matrix_destroy).  `aux` receives the sliced layout, the Jacobi
+ * scaling 1/diag(A) and, with SSPCG_MATRIX_FP32, FP32 copies of both.  The
+ * handle itself is a small host struct.  The call synchronizes `stream`.
  * Layout: 64-row slices, one row per lane.  A slice whose rows share one
  * list of at most 32 column offsets (col - row) stores that list once and
  * no column indices; other slices keep explicit columns, padded to their
@@ -161,26 +196,29 @@ void sspcg_default_params(sspcg_params* p);
  * the SpMV streams.  Every layout sums each row's entries in CSR order, so
  * the product does not depend on the layout.  SSPCG_MATRIX_FULL_STORAGE
  * keeps both triangles (for later non-symmetric value updates).
- * Solves use only the library's copy, but sspcg_matrix_update_values,
+ * Solves use only the copy in `aux`, but sspcg_matrix_update_values,
  * sspcg_csr_value_grad and the diffusion calls read the caller's row_ptr and
  * col again: keep them alive as long as the handle is used with those calls.
- * Returns SSPCG_ERR_ARG for a malformed pattern (checked on the device) and
- * SSPCG_ERR_BREAKDOWN when a diagonal entry is missing or not positive. */
+ * Returns SSPCG_ERR_ARG for a malformed pattern (checked on the device),
+ * SSPCG_ERR_BREAKDOWN when a diagonal entry is missing or not positive,
+ * SSPCG_ERR_NONFINITE for a NaN/Inf value and SSPCG_ERR_WORKSPACE when
+ * aux_bytes is too small. */
 int sspcg_matrix_create(int32_t n, int32_t nnz, const int32_t* row_ptr, const int32_t* col,
-                        const double* val, int32_t flags, sspcg_stream stream,
-                        sspcg_matrix** out);
+                        const double* val, int32_t flags, void* aux, size_t aux_bytes,
+                        sspcg_stream stream, sspcg_matrix** out);
 /* Replaces the values (same pattern): val is device double[nnz] in CSR
  * order.  Synchronizes `stream`.  The values are checked before anything is
  * changed: SSPCG_ERR_NONFINITE / SSPCG_ERR_BREAKDOWN as for create, and
  * SSPCG_ERR_UNSUPPORTED for values that are not symmetric when the matrix
  * stores one triangle; on an error the matrix keeps its old values. */
 int sspcg_matrix_update_values(sspcg_matrix* A, const double* val, sspcg_stream stream);
+/* Frees the host handle; `aux` stays the caller's. */
 int sspcg_matrix_destroy(sspcg_matrix* A);
 /* Size of the library's copy (host outputs, each may be NULL): n, nnz, the
  * stored slots of the sliced layout (nnz plus zero padding; with the
  * symmetric half storage one triangle and the diagonal), the number of
  * 64-row slices and how many of them use a shared offset list (no column
- * indices), the device bytes held, and 1 if only one triangle is stored. */
+ * indices), the bytes of `aux` in use, and 1 if only one triangle is stored. */
 int sspcg_matrix_info(const sspcg_matrix* A, int64_t* n, int64_t* nnz, int64_t* slots,
                       int64_t* slices, int64_t* shared_slices, int64_t* device_bytes,
                       int64_t* symmetric);
@@ -192,30 +230,37 @@ int sspcg_workspace_bytes(const sspcg_matrix* A, const sspcg_params* p, size_t* 
 /* s-step PCG, Algorithm 1 with Algorithm 2 and FGS Gram solves.
  *   b (device, double[n]); x (device, double[n]): x0 on entry, the solution
  *   on exit - the iterate at the first passing stop test.
- *   work (device, >= sspcg_workspace_bytes): scratch, contents undefined after.
- *   res (host, required), history (host, optional): per outer iteration k,
- *   3 doubles {relative residual after the x update, eta_alpha, eta_beta}
- *   (the reduced-system residuals of Sec. 3.4; 0 where not formed), room for
- *   3*max_outer doubles.  MIXED: per refinement the FP64 true relative
- *   residual, room for max_refine+1 doubles.
+ *   work (device, >= sspcg_workspace_bytes, 256-byte aligned): scratch,
+ *   contents undefined after.
+ *   poll (host, pinned, >= SSPCG_POLL_BYTES): the buffer the host reads the
+ *   device's stop flag through; contents undefined after.
+ *   res (host, required).
+ *   history (host, optional): per outer iteration k, 4 doubles {relative
+ *   residual after the x update, eta_alpha, eta_beta, conjugacy defect}:
+ *   eta_alpha = ||b1 - W alpha|| / ||b1|| and eta_beta = ||B2 - W beta||_F /
+ *   ||B2||_F are the reduced-system residuals of Sec. 3.4, and the defect is
+ *   ||B2 - W beta||_F, which equals ||Q_{k+1}^T A Q_k||_F in exact
+ *   arithmetic (B2 = -Q_k^T A Z and Q_{k+1} = Z + Q_k beta, Sec. 2); 0 where
+ *   not formed.  Room for 4*max_outer doubles.  MIXED: per refinement the
+ *   FP64 true relative residual, room for max_refine+1 doubles.
+ *   profile (host, optional): with p->profile = 1 the per-phase GPU time.
  * If ||b|| = 0 the result is x = 0 after no iteration; if the starting
  * residual already passes the test, x is returned unchanged.
  * On SSPCG_ERR_BREAKDOWN / SSPCG_ERR_NONFINITE, x holds the last iterate
- * before the failing Gram solve.  Blocks until done. */
+ * before the failing Gram solve.  Blocks until done.  The matrix handle is
+ * only read, so solves on one matrix with their own workspace and poll
+ * buffer may run at the same time. */
 int sspcg_solve(const sspcg_matrix* A, const double* b, double* x, const sspcg_params* p,
-                void* work, size_t work_bytes, sspcg_stream stream, sspcg_result* res,
-                double* history);
-
-/* Profile of the last sspcg_solve on A that ran with p->profile = 1
- * (zeros if none).  out: host struct. */
-int sspcg_last_profile(const sspcg_matrix* A, sspcg_profile* out);
+                void* work, size_t work_bytes, void* poll, sspcg_stream stream,
+                sspcg_result* res, double* history, sspcg_profile* profile);
 
 /* Classical Jacobi PCG (the method s-step PCG replaces), same stop test.
- * Uses p->tol, p->max_outer (as the iteration limit) and p->check_every.
+ * Uses p->tol, p->max_outer (as the iteration limit) and p->check_every;
+ * work and poll as for sspcg_solve.
  * history (host, optional): relative residual per iteration. */
 int sspcg_pcg_solve(const sspcg_matrix* A, const double* b, double* x, const sspcg_params* p,
-                    void* work, size_t work_bytes, sspcg_stream stream, sspcg_result* res,
-                    double* history);
+                    void* work, size_t work_bytes, void* poll, sspcg_stream stream,
+                    sspcg_result* res, double* history);
 
 /* ---------------------------------------------------------------- basis interval */
 /* The Chebyshev basis needs an interval [lambda_min, lambda_max] holding the

@@ -81,6 +81,7 @@ def lib():
         "or_block_update": (None, [_I64, _I, _P, _P, _P, _P, _P, _I64]),
         "or_block_update_f32": (None, [_I64, _I, _P, _P, _P, _P, _P, _I64]),
         "or_gram_relres": (_D, [_I, _I, _P, _P, _P]),
+        "or_gram_resnorm": (_D, [_I, _I, _P, _P, _P]),
         "or_sspcg": (_I, [_I64, _P, _P, _P, _P, _P, _I, _I, _D, _D, _D, _I, _I, _D, _I, _P, _P]),
         "or_pcg": (_I, [_I64, _P, _P, _P, _P, _P, _D, _I, _P, _P]),
         "or_sspcg_mixed": (_I, [_I64, _P, _P, _P, _P, _P, _I, _I, _D, _D, _D, _D, _I, _I,
@@ -236,12 +237,22 @@ def gram_relres(W, B, X) -> float:
     return lib().or_gram_relres(W.shape[0], B.shape[1], _p(W), _p(B), _p(X))
 
 
+def gram_resnorm(W, B, X) -> float:
+    """||B - W X||_F."""
+    W = _f64(W)
+    B = _f64(B).reshape(W.shape[0], -1)
+    X = _f64(X).reshape(W.shape[0], -1)
+    return lib().or_gram_resnorm(W.shape[0], B.shape[1], _p(W), _p(B), _p(X))
+
+
 def sspcg(A, b, x0=None, *, s, sweeps, interval, tol, max_outer=20000,
           gram="fgs", sweep_tol=0.0, basis="chebyshev", history=False):
-    """Algorithm 1.  Returns (x, result dict[, history (k, 3)])."""
+    """Algorithm 1.  Returns (x, result dict[, history (k, 4)]): per outer
+    iteration the relative residual, eta_alpha, eta_beta and the conjugacy
+    defect ||B2 - W beta||_F."""
     b = _f64(b)
     x = np.zeros(A.n) if x0 is None else _f64(x0).copy()
-    hist = np.zeros((max_outer, 3)) if history else None
+    hist = np.zeros((max_outer, 4)) if history else None
     res = Result()
     lib().or_sspcg(A.n, _p(A.row_ptr), _p(A.col), _p(A.val), _p(b), _p(x), s, sweeps,
                    interval[0], interval[1], tol, max_outer,

@@ -10,8 +10,9 @@
  * loops in the order the paper states the operations.  Dot products are
  * taken sequentially with Neumaier's compensated summation (A. Neumaier,
  * ZAMM 54, 1974) so that the oracle's own rounding error stays far below the
- * tolerances the GPU is held to.  Loops over independent rows may run in
- * parallel (OpenMP); that never changes a result.
+ * tolerances the GPU is held to.  Loops over independent rows, and the
+ * independent dot products of one Gram matrix (each still summed
+ * sequentially), may run in parallel (OpenMP); that never changes a result.
  *
  * Blocks of vectors are column-major: column j of an n x m block B is
  * B + j*ld.  Small s x s matrices are row-major: W[i*s + j].
@@ -163,6 +164,7 @@ void or_mpk_basis(int64_t n, const int32_t* rp, const int32_t* col, const double
     #define ZP(q) (zp + (int64_t)((q) - 1) * n)
     #define ZC(q) (Z + (int64_t)((q) - 1) * ld)
     #define PC(q) (P + (int64_t)((q) - 1) * ld)
+    #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i) {
         PC(1)[i] = r[i];
         ZP(1)[i] = PC(1)[i];
@@ -171,6 +173,7 @@ void or_mpk_basis(int64_t n, const int32_t* rp, const int32_t* col, const double
     if (basis == 1) {
         for (int q = 1; q <= s - 1; ++q) {
             or_spmv(n, rp, col, val, ZC(q), PC(q + 1));
+            #pragma omp parallel for schedule(static)
             for (int64_t i = 0; i < n; ++i) {
                 ZP(q + 1)[i] = PC(q + 1)[i];
                 ZC(q + 1)[i] = dinv[i] * ZP(q + 1)[i];
@@ -178,12 +181,14 @@ void or_mpk_basis(int64_t n, const int32_t* rp, const int32_t* col, const double
         }
     } else if (s > 1) {
         or_spmv(n, rp, col, val, ZC(1), PC(2));
+        #pragma omp parallel for schedule(static)
         for (int64_t i = 0; i < n; ++i) {
             ZP(2)[i] = al * PC(2)[i] - sg * ZP(1)[i];
             ZC(2)[i] = dinv[i] * ZP(2)[i];
         }
         for (int q = 2; q <= s - 1; ++q) {
             or_spmv(n, rp, col, val, ZC(q), PC(q + 1));
+            #pragma omp parallel for schedule(static)
             for (int64_t i = 0; i < n; ++i) {
                 ZP(q + 1)[i] = 2.0 * al * PC(q + 1)[i] - 2.0 * sg * ZP(q)[i] - gm * ZP(q - 1)[i];
                 ZC(q + 1)[i] = dinv[i] * ZP(q + 1)[i];
@@ -205,13 +210,21 @@ void or_mpk_basis(int64_t n, const int32_t* rp, const int32_t* col, const double
 void or_gram(int64_t n, int s, const double* Q, const double* AQ, const double* r,
              int64_t ld, double* W, double* b1)
 {
-    for (int i = 0; i < s; ++i) {
-        for (int j = 0; j <= i; ++j) {
-            const double w = or_dot(n, Q + (int64_t)i * ld, AQ + (int64_t)j * ld);
-            W[i * s + j] = w;
-            W[j * s + i] = w;
+    /* task t < s(s+1)/2: entry (i, j), i >= j, in row order; then b1_i */
+    const int nw = s * (s + 1) / 2;
+    #pragma omp parallel for schedule(dynamic, 1)
+    for (int t = 0; t < nw + s; ++t) {
+        if (t >= nw) {
+            const int i = t - nw;
+            b1[i] = or_dot(n, Q + (int64_t)i * ld, r);
+            continue;
         }
-        b1[i] = or_dot(n, Q + (int64_t)i * ld, r);
+        int i = 0;
+        while ((i + 1) * (i + 2) / 2 <= t) ++i;
+        const int j = t - i * (i + 1) / 2;
+        const double w = or_dot(n, Q + (int64_t)i * ld, AQ + (int64_t)j * ld);
+        W[i * s + j] = w;
+        W[j * s + i] = w;
     }
 }
 
@@ -219,9 +232,11 @@ void or_gram(int64_t n, int s, const double* Q, const double* AQ, const double* 
 void or_gram_rect(int64_t n, int s, const double* Q, const double* AZ, int64_t ld,
                   double* B2)
 {
-    for (int i = 0; i < s; ++i)
-        for (int j = 0; j < s; ++j)
-            B2[i * s + j] = -or_dot(n, Q + (int64_t)i * ld, AZ + (int64_t)j * ld);
+    #pragma omp parallel for schedule(dynamic, 1)
+    for (int t = 0; t < s * s; ++t) {
+        const int i = t / s, j = t % s;
+        B2[i * s + j] = -or_dot(n, Q + (int64_t)i * ld, AZ + (int64_t)j * ld);
+    }
 }
 
 /* ------------------------------------------------------------------ */
@@ -368,6 +383,21 @@ void or_block_update(int64_t n, int s, const double* Z, double* Q, const double*
 /* Diagnostics: relative residuals of the two reduced systems           */
 /* ------------------------------------------------------------------ */
 
+/* ||B - W X||_F, the absolute residual of the reduced system.  For the beta
+ * system it is the size of Q_{k+1}^T A Q_k: with B2 = -Q_k^T AZ and
+ * Q_{k+1} = Z + Q_k beta, Q_k^T A Q_{k+1} = -B2 + W beta (Sec. 2). */
+double or_gram_resnorm(int s, int nrhs, const double* W, const double* B, const double* X)
+{
+    double num = 0.0;
+    for (int c = 0; c < nrhs; ++c)
+        for (int i = 0; i < s; ++i) {
+            double t = B[i * nrhs + c];
+            for (int j = 0; j < s; ++j) t -= W[i * s + j] * X[j * nrhs + c];
+            num += t * t;
+        }
+    return sqrt(num);
+}
+
 /* ||m - W a||_2 / ||m||_2 for every column, combined in the Frobenius norm. */
 double or_gram_relres(int s, int nrhs, const double* W, const double* B, const double* X)
 {
@@ -388,9 +418,11 @@ double or_gram_relres(int s, int nrhs, const double* W, const double* B, const d
 
 /* Solves A x = b from x (in: x0, out: x).  gram = 0: FGS with `sweeps`
  * sweeps (or fewer once a column meets sweep_tol > 0, see or_fgs_tol);
- * gram = 1: Cholesky.  basis: 0 Chebyshev, 1 monomial (or_mpk_basis).  hist (optional, 3*max_outer doubles) receives
- * per outer iteration k: the relative residual after the x update,
- * eta_alpha and eta_beta (0 where no beta system was solved).
+ * gram = 1: Cholesky.  basis: 0 Chebyshev, 1 monomial (or_mpk_basis).
+ * hist (optional, 4*max_outer doubles) receives per outer iteration k: the
+ * relative residual after the x update, eta_alpha, eta_beta and the
+ * conjugacy defect ||B2 - W beta||_F (the last two 0 where no beta system
+ * was solved).
  * Stops when ||r|| <= tol ||b|| on the recursively updated residual.  If
  * ||b|| = 0 the solution is x = 0; if the starting residual already meets the
  * test no iteration is taken. */
@@ -446,9 +478,10 @@ int or_sspcg(int64_t n, const int32_t* rp, const int32_t* col, const double* val
         or_xr_update(n, s, Q, AQ, al, ld, x, r);
         relres = or_nrm2(n, r) / nb;
         if (hist) {
-            hist[3 * k] = relres;
-            hist[3 * k + 1] = or_gram_relres(s, 1, W, b1, al);
-            hist[3 * k + 2] = 0.0;
+            hist[4 * k] = relres;
+            hist[4 * k + 1] = or_gram_relres(s, 1, W, b1, al);
+            hist[4 * k + 2] = 0.0;
+            hist[4 * k + 3] = 0.0;
         }
         if (!isfinite(relres)) { status = OR_NONFINITE; k += 1; break; }
         if (relres <= tol) { status = OR_OK; k += 1; break; }
@@ -457,7 +490,10 @@ int or_sspcg(int64_t n, const int32_t* rp, const int32_t* col, const double* val
         or_gram_rect(n, s, Q, P + ld, ld, B2);
         st = gram ? or_chol_solve(s, s, W, B2, be)
                   : or_fgs_tol(s, s, W, B2, sweeps, sweep_tol, be);
-        if (hist) hist[3 * k + 2] = or_gram_relres(s, s, W, B2, be);
+        if (hist) {
+            hist[4 * k + 2] = or_gram_relres(s, s, W, B2, be);
+            hist[4 * k + 3] = or_gram_resnorm(s, s, W, B2, be);
+        }
         if (st != OR_OK) { status = st; k += 1; break; }
         or_block_update(n, s, Z, Q, P + ld, AQ, be, ld);
     }
@@ -573,6 +609,7 @@ void or_mpk_f32(int64_t n, const int32_t* rp, const int32_t* col, const float* v
     #define ZP(q) (zp + (int64_t)((q) - 1) * n)
     #define ZC(q) (Z + (int64_t)((q) - 1) * ld)
     #define PC(q) (P + (int64_t)((q) - 1) * ld)
+    #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i) {
         PC(1)[i] = r[i];
         ZP(1)[i] = PC(1)[i];
@@ -580,12 +617,14 @@ void or_mpk_f32(int64_t n, const int32_t* rp, const int32_t* col, const float* v
     }
     if (s > 1) {
         or_spmv_f32(n, rp, col, val, ZC(1), PC(2));
+        #pragma omp parallel for schedule(static)
         for (int64_t i = 0; i < n; ++i) {
             ZP(2)[i] = (float)(al * (double)PC(2)[i] - sg * (double)ZP(1)[i]);
             ZC(2)[i] = (float)((double)dinv[i] * (double)ZP(2)[i]);
         }
         for (int q = 2; q <= s - 1; ++q) {
             or_spmv_f32(n, rp, col, val, ZC(q), PC(q + 1));
+            #pragma omp parallel for schedule(static)
             for (int64_t i = 0; i < n; ++i) {
                 ZP(q + 1)[i] = (float)(2.0 * al * (double)PC(q + 1)[i] - 2.0 * sg * (double)ZP(q)[i]
                                        - gm * (double)ZP(q - 1)[i]);
@@ -603,22 +642,32 @@ void or_mpk_f32(int64_t n, const int32_t* rp, const int32_t* col, const float* v
 void or_gram_f32(int64_t n, int s, const float* Q, const float* AQ, const float* r,
                  int64_t ld, double* W, double* b1)
 {
-    for (int i = 0; i < s; ++i) {
-        for (int j = 0; j <= i; ++j) {
-            const double w = dot_f32(n, Q + (int64_t)i * ld, AQ + (int64_t)j * ld);
-            W[i * s + j] = w;
-            W[j * s + i] = w;
+    /* the tasks of or_gram */
+    const int nw = s * (s + 1) / 2;
+    #pragma omp parallel for schedule(dynamic, 1)
+    for (int t = 0; t < nw + s; ++t) {
+        if (t >= nw) {
+            const int i = t - nw;
+            b1[i] = dot_f32(n, Q + (int64_t)i * ld, r);
+            continue;
         }
-        b1[i] = dot_f32(n, Q + (int64_t)i * ld, r);
+        int i = 0;
+        while ((i + 1) * (i + 2) / 2 <= t) ++i;
+        const int j = t - i * (i + 1) / 2;
+        const double w = dot_f32(n, Q + (int64_t)i * ld, AQ + (int64_t)j * ld);
+        W[i * s + j] = w;
+        W[j * s + i] = w;
     }
 }
 
 void or_gram_rect_f32(int64_t n, int s, const float* Q, const float* AZ, int64_t ld,
                       double* B2)
 {
-    for (int i = 0; i < s; ++i)
-        for (int j = 0; j < s; ++j)
-            B2[i * s + j] = -dot_f32(n, Q + (int64_t)i * ld, AZ + (int64_t)j * ld);
+    #pragma omp parallel for schedule(dynamic, 1)
+    for (int t = 0; t < s * s; ++t) {
+        const int i = t / s, j = t % s;
+        B2[i * s + j] = -dot_f32(n, Q + (int64_t)i * ld, AZ + (int64_t)j * ld);
+    }
 }
 
 void or_xr_update_f32(int64_t n, int s, const float* Q, const float* AQ,

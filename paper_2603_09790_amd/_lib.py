@@ -16,12 +16,15 @@ BASIS = {"chebyshev": 0, "monomial": 1}
 MATRIX_FP32 = 1
 MATRIX_FULL_STORAGE = 2
 MAX_S = 16
+POLL_BYTES = 256      # SSPCG_POLL_BYTES
+HIST_STRIDE = 4       # doubles per outer iteration in the s-step history
 
 # Every symbol the header declares, in header order.
 EXPORTS = [
     "sspcg_abi_version", "sspcg_status_string", "sspcg_last_error", "sspcg_default_params",
+    "sspcg_matrix_scratch_bytes", "sspcg_matrix_aux_bytes",
     "sspcg_matrix_create", "sspcg_matrix_update_values", "sspcg_matrix_destroy",
-    "sspcg_matrix_info", "sspcg_workspace_bytes", "sspcg_solve", "sspcg_last_profile",
+    "sspcg_matrix_info", "sspcg_workspace_bytes", "sspcg_solve",
     "sspcg_pcg_solve", "sspcg_interval_work_bytes", "sspcg_interval",
     "sspcg_kernel_work_bytes", "sspcg_spmv", "sspcg_mpk", "sspcg_block_update_gram",
     "sspcg_gram_rect", "sspcg_fgs", "sspcg_xr_update", "sspcg_csr_value_grad",
@@ -42,8 +45,9 @@ class Params(ctypes.Structure):
 
 class Result(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("outer_iters", ctypes.c_int32),
-                ("refinements", ctypes.c_int32), ("reserved", ctypes.c_int32),
-                ("relres", ctypes.c_double), ("device_ms", ctypes.c_double)]
+                ("refinements", ctypes.c_int32), ("inner_iters_total", ctypes.c_int32),
+                ("relres", ctypes.c_double), ("relres_true", ctypes.c_double),
+                ("device_ms", ctypes.c_double)]
 
 
 PHASES = ["spmv", "gram_update", "gram_rect", "fgs", "norm", "xr"]
@@ -82,15 +86,18 @@ def lib() -> ctypes.CDLL:
         "sspcg_status_string": (ctypes.c_char_p, [ctypes.c_int]),
         "sspcg_last_error": (ctypes.c_char_p, []),
         "sspcg_default_params": (None, [ctypes.POINTER(Params)]),
-        "sspcg_matrix_create": (ctypes.c_int, [I32, I32, P, P, P, I32, P, ctypes.POINTER(P)]),
+        "sspcg_matrix_scratch_bytes": (SZ, [I32]),
+        "sspcg_matrix_aux_bytes": (ctypes.c_int, [I32, I32, P, P, P, I32, P, SZ, P,
+                                                  ctypes.POINTER(SZ)]),
+        "sspcg_matrix_create": (ctypes.c_int, [I32, I32, P, P, P, I32, P, SZ, P,
+                                               ctypes.POINTER(P)]),
         "sspcg_matrix_update_values": (ctypes.c_int, [P, P, P]),
         "sspcg_matrix_destroy": (ctypes.c_int, [P]),
         "sspcg_matrix_info": (ctypes.c_int, [P] + [ctypes.POINTER(I64)] * 7),
         "sspcg_workspace_bytes": (ctypes.c_int, [P, ctypes.POINTER(Params), ctypes.POINTER(SZ)]),
-        "sspcg_solve": (ctypes.c_int, [P, P, P, ctypes.POINTER(Params), P, SZ, P,
-                                       ctypes.POINTER(Result), P]),
-        "sspcg_last_profile": (ctypes.c_int, [P, ctypes.POINTER(Profile)]),
-        "sspcg_pcg_solve": (ctypes.c_int, [P, P, P, ctypes.POINTER(Params), P, SZ, P,
+        "sspcg_solve": (ctypes.c_int, [P, P, P, ctypes.POINTER(Params), P, SZ, P, P,
+                                       ctypes.POINTER(Result), P, ctypes.POINTER(Profile)]),
+        "sspcg_pcg_solve": (ctypes.c_int, [P, P, P, ctypes.POINTER(Params), P, SZ, P, P,
                                            ctypes.POINTER(Result), P]),
         "sspcg_interval_work_bytes": (ctypes.c_int, [P, I32, ctypes.POINTER(SZ)]),
         "sspcg_interval": (ctypes.c_int, [P, I32, I32, D, P, P, SZ, P, ctypes.POINTER(D),

@@ -17,6 +17,7 @@
 #include <cstring>
 #include <exception>
 #include <functional>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -63,6 +64,13 @@ namespace {
         return SSPCG_ERR_HIP;                      \
     }
 
+#define RETURN_IF(x)                \
+    do {                            \
+        int rc_ = (x);              \
+        if (rc_ != SSPCG_OK) return rc_; \
+    } while (0)
+
+
 inline hipStream_t as_stream(sspcg_stream s) { return reinterpret_cast<hipStream_t>(s); }
 
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
@@ -105,7 +113,7 @@ Workspace layout_sspcg(int64_t n, const sspcg_params* p)
     w.part = off;
     off += partial_bytes(s);
     w.hist = off;
-    off += align_up(sizeof(double) * 3 * (size_t)std::max(p->max_outer, 1), 256);
+    off += align_up(sizeof(double) * kHistStride * (size_t)std::max(p->max_outer, 1), 256);
     w.vec = off;
     // r, Z, AZ, Q, AQ (+ the correction d of the mixed form)
     w.ncols = 4 * s + 1 + (p->precision == SSPCG_MIXED ? 1 : 0);
@@ -355,7 +363,8 @@ int enqueue_mpk(const sspcg_matrix* A, int s, int basis, double al, double sg, T
 // residual, Z(:,1) = M^{-1} r and the device Ctrl is initialized.
 template <typename T>
 int run_sspcg(const sspcg_matrix* A, const sspcg_params* p, const Workspace& w, char* base, T* x,
-              const T* dinv, int64_t max_iter, double* dhist, hipStream_t st)
+              const T* dinv, int64_t max_iter, double* dhist, Ctrl* hctrl, sspcg_profile* prof,
+              hipStream_t st)
 {
     const int s = p->s;
     const int64_t n = A->n, ld = w.ld;
@@ -433,21 +442,21 @@ int run_sspcg(const sspcg_matrix* A, const sspcg_params* p, const Workspace& w, 
             return e == hipSuccess ? SSPCG_OK : hip_fail(e, "hipGraphLaunch");
         };
         const int64_t batches = (max_iter + p->check_every - 1) / p->check_every;
-        rc = run_polled(ctrl, A->host_ctrl, batches * p->check_every, p->check_every, st, replay);
+        rc = run_polled(ctrl, hctrl, batches * p->check_every, p->check_every, st, replay);
         (void)hipGraphExecDestroy(exec);
         (void)hipGraphDestroy(graph);
         if (rc == SSPCG_OK) rc = launch_x_pending<T>(n, s, Q, alpha, ld, x, ctrl, st);
         return rc;
     }
-    rc = run_polled(ctrl, A->host_ctrl, max_iter, p->check_every, st, step, on_batch);
-    if (rc == SSPCG_OK) tm.fill(const_cast<sspcg_profile*>(&A->profile), s, A->host_ctrl[0].iter);
+    rc = run_polled(ctrl, hctrl, max_iter, p->check_every, st, step, on_batch);
+    if (rc == SSPCG_OK && prof) tm.fill(prof, s, hctrl[0].iter);
     if (rc == SSPCG_OK) rc = launch_x_pending<T>(n, s, Q, alpha, ld, x, ctrl, st);
     return rc;
 }
 
 // Writes the initial control block through the pinned mirror.
-int init_ctrl(const sspcg_matrix* A, Ctrl* dctrl, double nb, double tol, int64_t max_iter,
-              double rho0, hipStream_t st)
+int init_ctrl(Ctrl* hctrl, Ctrl* dctrl, double nb, double tol, int64_t max_iter, double rho0,
+              hipStream_t st)
 {
     Ctrl c;
     std::memset(&c, 0, sizeof(c));
@@ -459,20 +468,19 @@ int init_ctrl(const sspcg_matrix* A, Ctrl* dctrl, double nb, double tol, int64_t
     c.tol = tol;
     c.relres = 0.0;
     c.rho[0] = rho0;
-    A->host_ctrl[0] = c;
-    SSPCG_HIP(hipMemcpyAsync(dctrl, &A->host_ctrl[0], sizeof(Ctrl), hipMemcpyHostToDevice, st));
+    hctrl[0] = c;
+    SSPCG_HIP(hipMemcpyAsync(dctrl, &hctrl[0], sizeof(Ctrl), hipMemcpyHostToDevice, st));
     return SSPCG_OK;
 }
 
 // Reads the setup sums {||b-Ax||^2, ||r_stored||^2, ||b||^2, r^T z} (blocking).
-int setup_sums(const sspcg_matrix* A, Ctrl* dctrl, const double* part, int G, double* out,
-               hipStream_t st)
+int setup_sums(Ctrl* hctrl, Ctrl* dctrl, const double* part, int G, double* out, hipStream_t st)
 {
     int rc = launch_finish(part, 4, G, dctrl->sums, st);
     if (rc != SSPCG_OK) return rc;
-    SSPCG_HIP(hipMemcpyAsync(&A->host_ctrl[1], dctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
+    SSPCG_HIP(hipMemcpyAsync(&hctrl[1], dctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
     SSPCG_HIP(hipStreamSynchronize(st));
-    for (int i = 0; i < 4; ++i) out[i] = A->host_ctrl[1].sums[i];
+    for (int i = 0; i < 4; ++i) out[i] = hctrl[1].sums[i];
     return SSPCG_OK;
 }
 
@@ -498,8 +506,23 @@ struct Timer {
     }
 };
 
+// ||b - A x|| / ||b|| in FP64 for the returned x (r and part are free
+// workspace once the iteration has ended); not part of the timed solve.
+int true_relres(const sspcg_matrix* A, const double* b, const double* x, double* r, double* part,
+                Ctrl* dctrl, Ctrl* hctrl, hipStream_t st, double* out)
+{
+    int G = 0;
+    double sums[4];
+    int rc = launch_residual<double>(A, x, b, r, static_cast<double*>(nullptr), part, &G, st);
+    if (rc == SSPCG_OK) rc = setup_sums(hctrl, dctrl, part, G, sums, st);
+    if (rc != SSPCG_OK) return rc;
+    *out = sums[2] > 0.0 ? std::sqrt(sums[0]) / std::sqrt(sums[2]) : 0.0;
+    return SSPCG_OK;
+}
+
 int solve_fp64(const sspcg_matrix* A, const double* b, double* x, const sspcg_params* p,
-               const Workspace& w, char* base, hipStream_t st, sspcg_result* res, double* history)
+               const Workspace& w, char* base, Ctrl* hctrl, hipStream_t st, sspcg_result* res,
+               double* history, sspcg_profile* prof)
 {
     Ctrl* ctrl = reinterpret_cast<Ctrl*>(base + w.ctrl);
     double* part = reinterpret_cast<double*>(base + w.part);
@@ -510,43 +533,49 @@ int solve_fp64(const sspcg_matrix* A, const double* b, double* x, const sspcg_pa
     int G = 0;
     int rc = launch_residual<double>(A, x, b, r, Z, part, &G, st);
     double sums[4];
-    if (rc == SSPCG_OK) rc = setup_sums(A, ctrl, part, G, sums, st);
+    if (rc == SSPCG_OK) rc = setup_sums(hctrl, ctrl, part, G, sums, st);
     if (rc != SSPCG_OK) return rc;
     const double nb = std::sqrt(sums[2]);
     res->outer_iters = 0;
     if (!std::isfinite(nb) || !std::isfinite(sums[0])) {
         res->device_ms = tm.stop();
+        res->relres = res->relres_true = std::sqrt(sums[0]) / nb;
         set_error("non-finite right-hand side or starting residual");
         return res->status = SSPCG_ERR_NONFINITE;
     }
     if (nb == 0.0) {
         rc = launch_fill<double>(A->n, x, 0.0, st);
         res->device_ms = tm.stop();
-        res->relres = 0.0;
+        res->relres = res->relres_true = 0.0;
         return res->status = rc;
     }
     const double rel0 = std::sqrt(sums[0]) / nb;
     if (rel0 <= p->tol) {
         res->device_ms = tm.stop();
-        res->relres = rel0;
+        res->relres = res->relres_true = rel0;
         return res->status = SSPCG_OK;
     }
-    rc = init_ctrl(A, ctrl, nb, p->tol, p->max_outer, 0.0, st);
+    rc = init_ctrl(hctrl, ctrl, nb, p->tol, p->max_outer, 0.0, st);
     if (rc == SSPCG_OK)
-        rc = run_sspcg<double>(A, p, w, base, x, A->dinv, p->max_outer, history ? dhist : nullptr, st);
+        rc = run_sspcg<double>(A, p, w, base, x, A->dinv, p->max_outer, history ? dhist : nullptr,
+                               hctrl, prof, st);
     res->device_ms = tm.stop();
     if (rc != SSPCG_OK) return res->status = rc;
-    const Ctrl& c = A->host_ctrl[0];
+    const Ctrl c = hctrl[0];
     res->outer_iters = c.iter;
+    res->inner_iters_total = c.iter;
     res->relres = c.relres;
     res->status = c.done ? c.status : SSPCG_NOT_CONVERGED;
     if (history && c.iter > 0)
-        SSPCG_HIP(hipMemcpy(history, dhist, sizeof(double) * 3 * (size_t)c.iter, hipMemcpyDeviceToHost));
+        SSPCG_HIP(hipMemcpy(history, dhist, sizeof(double) * kHistStride * (size_t)c.iter,
+                            hipMemcpyDeviceToHost));
+    RETURN_IF(true_relres(A, b, x, r, part, ctrl, hctrl, st, &res->relres_true));
     return res->status;
 }
 
 int solve_mixed(const sspcg_matrix* A, const double* b, double* x, const sspcg_params* p,
-                const Workspace& w, char* base, hipStream_t st, sspcg_result* res, double* history)
+                const Workspace& w, char* base, Ctrl* hctrl, hipStream_t st, sspcg_result* res,
+                double* history, sspcg_profile* prof)
 {
     Ctrl* ctrl = reinterpret_cast<Ctrl*>(base + w.ctrl);
     double* part = reinterpret_cast<double*>(base + w.part);
@@ -560,12 +589,13 @@ int solve_mixed(const sspcg_matrix* A, const double* b, double* x, const sspcg_p
         int G = 0;
         double sums[4];
         int rc = launch_residual<float>(A, x, b, r, Z, part, &G, st);
-        if (rc == SSPCG_OK) rc = setup_sums(A, ctrl, part, G, sums, st);
+        if (rc == SSPCG_OK) rc = setup_sums(hctrl, ctrl, part, G, sums, st);
         if (rc != SSPCG_OK) return rc;
         if (nref == 0) {
             nb = std::sqrt(sums[2]);
             if (!std::isfinite(nb)) {
                 status = SSPCG_ERR_NONFINITE;
+                relres = nb;
                 set_error("non-finite right-hand side");
                 break;
             }
@@ -593,11 +623,13 @@ int solve_mixed(const sspcg_matrix* A, const double* b, double* x, const sspcg_p
         }
         // reduce by inner_tol, or only to half the outer target when closer
         const double itol = std::min(std::max(p->inner_tol, 0.5 * p->tol / relres), 0.5);
-        rc = init_ctrl(A, ctrl, std::sqrt(sums[1]), itol, p->max_outer, 0.0, st);
+        rc = init_ctrl(hctrl, ctrl, std::sqrt(sums[1]), itol, p->max_outer, 0.0, st);
         if (rc == SSPCG_OK) rc = launch_fill<float>(A->n, d, 0.0f, st);
-        if (rc == SSPCG_OK) rc = run_sspcg<float>(A, p, w, base, d, A->dinv32, p->max_outer, nullptr, st);
+        if (rc == SSPCG_OK)
+            rc = run_sspcg<float>(A, p, w, base, d, A->dinv32, p->max_outer, nullptr, hctrl, prof,
+                                  st);
         if (rc != SSPCG_OK) return rc;
-        const Ctrl& c = A->host_ctrl[0];
+        const Ctrl c = hctrl[0];
         inner_total += c.iter;
         if (c.status != SSPCG_OK && c.status != SSPCG_NOT_CONVERGED) {
             status = c.status;
@@ -609,13 +641,16 @@ int solve_mixed(const sspcg_matrix* A, const double* b, double* x, const sspcg_p
     }
     res->device_ms = tm.stop();
     res->outer_iters = inner_total;
+    res->inner_iters_total = inner_total;
     res->refinements = nref;
-    res->relres = relres;
+    // the outer stop test is on the FP64 true residual of the returned x
+    res->relres = res->relres_true = relres;
     return res->status = status;
 }
 
 int solve_pcg(const sspcg_matrix* A, const double* b, double* x, const sspcg_params* p,
-              const Workspace& w, char* base, hipStream_t st, sspcg_result* res, double* history)
+              const Workspace& w, char* base, Ctrl* hctrl, hipStream_t st, sspcg_result* res,
+              double* history)
 {
     Ctrl* ctrl = reinterpret_cast<Ctrl*>(base + w.ctrl);
     double* part = reinterpret_cast<double*>(base + w.part);
@@ -630,27 +665,29 @@ int solve_pcg(const sspcg_matrix* A, const double* b, double* x, const sspcg_par
     int G = 0;
     double sums[4];
     int rc = launch_residual<double>(A, x, b, r, z, part2, &G, st);
-    if (rc == SSPCG_OK) rc = setup_sums(A, ctrl, part2, G, sums, st);
+    if (rc == SSPCG_OK) rc = setup_sums(hctrl, ctrl, part2, G, sums, st);
     if (rc != SSPCG_OK) return rc;
     const double nb = std::sqrt(sums[2]);
     res->outer_iters = 0;
     if (!std::isfinite(nb) || !std::isfinite(sums[0])) {
         res->device_ms = tm.stop();
+        res->relres = res->relres_true = std::sqrt(sums[0]) / nb;
         set_error("non-finite right-hand side or starting residual");
         return res->status = SSPCG_ERR_NONFINITE;
     }
     if (nb == 0.0) {
         rc = launch_fill<double>(n, x, 0.0, st);
         res->device_ms = tm.stop();
+        res->relres = res->relres_true = 0.0;
         return res->status = rc;
     }
     const double rel0 = std::sqrt(sums[0]) / nb;
     if (rel0 <= p->tol) {
         res->device_ms = tm.stop();
-        res->relres = rel0;
+        res->relres = res->relres_true = rel0;
         return res->status = SSPCG_OK;
     }
-    rc = init_ctrl(A, ctrl, nb, p->tol, p->max_outer, sums[3], st);
+    rc = init_ctrl(hctrl, ctrl, nb, p->tol, p->max_outer, sums[3], st);
     if (rc != SSPCG_OK) return rc;
     SSPCG_HIP(hipMemcpyAsync(pv, z, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
     double* hist = history ? dhist : nullptr;
@@ -661,15 +698,17 @@ int solve_pcg(const sspcg_matrix* A, const double* b, double* x, const sspcg_par
         if (e == SSPCG_OK) e = launch_pcg_pupdate(n, k, z, pv, part2, g2, ctrl, hist, st);
         return e;
     };
-    rc = run_polled(ctrl, A->host_ctrl, p->max_outer, p->check_every, st, step);
+    rc = run_polled(ctrl, hctrl, p->max_outer, p->check_every, st, step);
     res->device_ms = tm.stop();
     if (rc != SSPCG_OK) return res->status = rc;
-    const Ctrl& c = A->host_ctrl[0];
+    const Ctrl c = hctrl[0];
     res->outer_iters = c.iter;
+    res->inner_iters_total = c.iter;
     res->relres = c.relres;
     res->status = c.done ? c.status : SSPCG_NOT_CONVERGED;
     if (history && c.iter > 0)
         SSPCG_HIP(hipMemcpy(history, dhist, sizeof(double) * (size_t)c.iter, hipMemcpyDeviceToHost));
+    RETURN_IF(true_relres(A, b, x, z, part2, ctrl, hctrl, st, &res->relres_true));
     return res->status;
 }
 
@@ -707,11 +746,89 @@ int check_work(void* work, size_t bytes, int s)
     return SSPCG_OK;
 }
 
-#define RETURN_IF(x)                \
-    do {                            \
-        int rc_ = (x);              \
-        if (rc_ != SSPCG_OK) return rc_; \
-    } while (0)
+
+int check_csr_args(int32_t n, int32_t nnz, const int32_t* row_ptr, const int32_t* col,
+                   const double* val, int32_t flags)
+{
+    if (n < 1 || nnz < n) return arg_error("need n >= 1 and nnz >= n (diagonal stored)");
+    if (!row_ptr || !col || !val) return arg_error("CSR pointer is NULL");
+    if (!aligned(row_ptr, 4) || !aligned(col, 4) || !aligned(val, 8)) return arg_error("CSR array misaligned");
+    if (flags & ~(SSPCG_MATRIX_FP32 | SSPCG_MATRIX_FULL_STORAGE)) return arg_error("unknown flag");
+    return SSPCG_OK;
+}
+
+// Places of the matrix's arrays in the caller's `aux` buffer (byte offsets,
+// each 256-byte aligned).  The analysis area and the Jacobi scaling come
+// first and depend on n alone; the layout's arrays follow the plan.
+struct AuxLayout {
+    size_t dinv = 0, dinv32 = 0, fixed = 0;
+    size_t slice_ptr = 0, slice_aux = 0, col = 0, soff = 0;   // per-slice layout
+    size_t uoff = 0;                                           // uniform layout
+    size_t val = 0, val32 = 0;
+    int64_t slots = 0;                                         // uniform: stored slots
+    size_t total = 0;                                          // 0: too large
+};
+
+AuxLayout aux_layout(const sspcg_matrix* A, const LayoutPlan& plan)
+{
+    AuxLayout L;
+    const bool f32 = (A->flags & SSPCG_MATRIX_FP32) != 0;
+    const int64_t rows = A->nslices * kSlice;
+    size_t off = analysis_bytes(A->n);
+    L.dinv = off;
+    off += align_up(sizeof(double) * (size_t)A->n, 256);
+    L.dinv32 = off;
+    if (f32) off += align_up(sizeof(float) * (size_t)A->n, 256);
+    L.fixed = off;
+    if (!plan.uoff.empty()) {
+        const int64_t uw = (int64_t)plan.uoff.size();
+        const int64_t stored = uw - (plan.usym ? uw / 2 : 0);
+        // the full storage groups FP64 values in pairs and FP32 values in
+        // quads; the half storage keeps single values
+        const int64_t stored64 = plan.usym ? stored : (stored + 1) / 2 * 2;
+        const int64_t stored32 = plan.usym ? stored : (stored + 3) / 4 * 4;
+        L.slots = rows * stored;
+        if (rows * stored64 >= ((int64_t)1 << 40)) return L;
+        L.uoff = off;
+        off += 256;
+        L.val = off;
+        off += align_up(sizeof(double) * (size_t)(rows * stored64), 256);
+        L.val32 = off;
+        if (f32) off += align_up(sizeof(float) * (size_t)(rows * stored32), 256);
+    } else if (!plan.slice_ptr.empty()) {
+        if (plan.slots >= ((int64_t)1 << 40)) return L;
+        L.slice_ptr = off;
+        off += align_up(sizeof(int64_t) * (size_t)(A->nslices + 1), 256);
+        L.slice_aux = off;
+        off += align_up(sizeof(int64_t) * (size_t)A->nslices, 256);
+        L.col = off;
+        off += align_up(sizeof(int32_t) * (size_t)plan.ncol, 256);
+        L.soff = off;
+        off += align_up(sizeof(int32_t) * (size_t)plan.nsoff, 256);
+        L.val = off;
+        off += align_up(sizeof(double) * (size_t)plan.slots, 256);
+        L.val32 = off;
+        if (f32) off += align_up(sizeof(float) * (size_t)plan.slots, 256);
+    }
+    L.total = off;
+    return L;
+}
+
+// The poll buffer must be pinned host memory: the pipelined polling copies
+// into it asynchronously.
+int check_poll(void* poll)
+{
+    if (!poll) return arg_error("poll is NULL (pinned host memory of SSPCG_POLL_BYTES bytes)");
+    if (!aligned(poll, 64)) return arg_error("poll must be 64-byte aligned");
+    hipPointerAttribute_t at;
+    const hipError_t e = hipPointerGetAttributes(&at, poll);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return arg_error("poll is not pinned host memory (hipHostMalloc or pin_memory)");
+    }
+    if (at.type != hipMemoryTypeHost) return arg_error("poll must be pinned host memory");
+    return SSPCG_OK;
+}
 
 }  // namespace
 
@@ -757,18 +874,53 @@ void sspcg_default_params(sspcg_params* p)
     p->use_graph = 0;
 }
 
+size_t sspcg_matrix_scratch_bytes(int32_t n)
+{
+    return analysis_bytes(std::max<int64_t>(n, 1));
+}
+
+int sspcg_matrix_aux_bytes(int32_t n, int32_t nnz, const int32_t* row_ptr, const int32_t* col,
+                           const double* val, int32_t flags, void* scratch, size_t scratch_bytes,
+                           sspcg_stream stream, size_t* aux_bytes)
+{
+    API_TRY
+    if (!aux_bytes) return arg_error("aux_bytes is NULL");
+    *aux_bytes = 0;
+    RETURN_IF(check_csr_args(n, nnz, row_ptr, col, val, flags));
+    if (!scratch || !aligned(scratch, 256)) return arg_error("scratch is NULL or not 256-byte aligned");
+    if (scratch_bytes < analysis_bytes(n)) {
+        set_error("scratch smaller than sspcg_matrix_scratch_bytes(n)");
+        return SSPCG_ERR_WORKSPACE;
+    }
+    sspcg_matrix A;
+    A.n = n;
+    A.nnz = nnz;
+    A.flags = flags;
+    A.row_ptr = row_ptr;
+    A.col = col;
+    A.nslices = (n + kSlice - 1) / kSlice;
+    bind_analysis(&A, scratch);
+    LayoutPlan plan;
+    RETURN_IF(matrix_inspect(&A, val, false, &plan, as_stream(stream), false,
+                             (flags & SSPCG_MATRIX_FULL_STORAGE) == 0));
+    const AuxLayout L = aux_layout(&A, plan);
+    if (L.total == 0) return arg_error("matrix too large");
+    *aux_bytes = L.total;
+    return SSPCG_OK;
+    API_CATCH
+}
+
 int sspcg_matrix_create(int32_t n, int32_t nnz, const int32_t* row_ptr, const int32_t* col,
-                        const double* val, int32_t flags, sspcg_stream stream, sspcg_matrix** out)
+                        const double* val, int32_t flags, void* aux, size_t aux_bytes,
+                        sspcg_stream stream, sspcg_matrix** out)
 {
     API_TRY
     if (!out) return arg_error("out is NULL");
     *out = nullptr;
-    if (n < 1 || nnz < n) return arg_error("need n >= 1 and nnz >= n (diagonal stored)");
-    if (!row_ptr || !col || !val) return arg_error("CSR pointer is NULL");
-    if (!aligned(row_ptr, 4) || !aligned(col, 4) || !aligned(val, 8)) return arg_error("CSR array misaligned");
-    if (flags & ~(SSPCG_MATRIX_FP32 | SSPCG_MATRIX_FULL_STORAGE)) return arg_error("unknown flag");
+    RETURN_IF(check_csr_args(n, nnz, row_ptr, col, val, flags));
+    if (!aux || !aligned(aux, 256)) return arg_error("aux is NULL or not 256-byte aligned");
     hipStream_t st = as_stream(stream);
-    auto* A = new sspcg_matrix();
+    std::unique_ptr<sspcg_matrix> A(new sspcg_matrix());
     A->n = n;
     A->nnz = nnz;
     A->flags = flags;
@@ -776,103 +928,58 @@ int sspcg_matrix_create(int32_t n, int32_t nnz, const int32_t* row_ptr, const in
     A->col = col;
     (void)hipGetDevice(&A->device);
     A->nslices = (n + kSlice - 1) / kSlice;
-    const bool f32 = (flags & SSPCG_MATRIX_FP32) != 0;
-    auto fail = [&](int rc) {
-        if (A->mem) (void)hipFree(A->mem);
-        if (A->mem_vals) (void)hipFree(A->mem_vals);
-        if (A->host_ctrl) (void)hipHostFree(A->host_ctrl);
-        delete A;
-        return rc;
-    };
-    const size_t b_sp = align_up(sizeof(int64_t) * (A->nslices + 1), 256);
-    const size_t b_aux = align_up(sizeof(int64_t) * A->nslices, 256);
-    const size_t b_dinv = align_up(sizeof(double) * (size_t)n, 256);
-    const size_t b_dinv32 = f32 ? align_up(sizeof(float) * (size_t)n, 256) : 0;
-    const size_t b_small = b_sp + b_aux + b_dinv + b_dinv32 + 256;
-    hipError_t e = hipMalloc(&A->mem, b_small);
-    if (e != hipSuccess) return fail(hip_fail(e, "hipMalloc(matrix)"));
-    char* m = static_cast<char*>(A->mem);
-    A->slice_ptr = reinterpret_cast<int64_t*>(m);
-    A->slice_aux = reinterpret_cast<int64_t*>(m + b_sp);
-    A->dinv = reinterpret_cast<double*>(m + b_sp + b_aux);
-    A->dinv32 = f32 ? reinterpret_cast<float*>(m + b_sp + b_aux + b_dinv) : nullptr;
-    A->dflags = reinterpret_cast<int32_t*>(m + b_sp + b_aux + b_dinv + b_dinv32);
-    e = hipHostMalloc((void**)&A->host_ctrl, 2 * sizeof(Ctrl), hipHostMallocDefault);
-    if (e != hipSuccess) return fail(hip_fail(e, "hipHostMalloc"));
+    A->aux = aux;
+    char* base = static_cast<char*>(aux);
+    // the analysis area and the Jacobi scaling have fixed places: the first
+    // pass over the matrix checks it and writes 1/diag(A)
+    const AuxLayout L0 = aux_layout(A.get(), LayoutPlan());
+    if (aux_bytes < L0.fixed) {
+        set_error("aux smaller than sspcg_matrix_aux_bytes reported");
+        return SSPCG_ERR_WORKSPACE;
+    }
+    bind_analysis(A.get(), base);
+    A->dinv = reinterpret_cast<double*>(base + L0.dinv);
+    A->dinv32 = (flags & SSPCG_MATRIX_FP32) ? reinterpret_cast<float*>(base + L0.dinv32) : nullptr;
     LayoutPlan plan;
-    int32_t* d_union = nullptr;
-    int rc = matrix_inspect(A, val, false, &plan, &d_union, st, true,
-                            (flags & SSPCG_MATRIX_FULL_STORAGE) == 0);
-    auto fail_union = [&](int r) {
-        if (d_union) {
-            (void)hipFreeAsync(d_union, st);
-            (void)hipStreamSynchronize(st);
-        }
-        return fail(r);
-    };
-    if (rc != SSPCG_OK) return fail_union(rc);
+    RETURN_IF(matrix_inspect(A.get(), val, false, &plan, st, true,
+                             (flags & SSPCG_MATRIX_FULL_STORAGE) == 0));
+    const AuxLayout L = aux_layout(A.get(), plan);
+    if (L.total == 0) return arg_error("matrix too large");
+    if (aux_bytes < L.total) {
+        set_error("aux smaller than sspcg_matrix_aux_bytes reported");
+        return SSPCG_ERR_WORKSPACE;
+    }
+    A->aux_used = L.total;
     A->slots = plan.slots;
     A->nshared = plan.nshared;
-    if (A->slots >= ((int64_t)1 << 40)) return fail_union(arg_error("matrix too large"));
     if (!plan.uoff.empty()) {
-        // uniform layout: offsets and vector-grouped values only
+        // uniform layout: offsets and values only
         A->uniform = 1;
         A->uw = (int32_t)plan.uoff.size();
         A->usym = plan.usym ? 1 : 0;
-        const int64_t stored = A->uw - (A->usym ? A->uw / 2 : 0);
-        A->slots = A->nslices * kSlice * stored;
-        const int64_t rows = A->nslices * kSlice;
-        const size_t b_uoff = 256;
-        const int64_t stored64 = A->usym ? stored : (stored + 1) / 2 * 2;   // FP64 half: no grouping
-        const size_t b_val = align_up(sizeof(double) * (size_t)rows * stored64, 256);
-        const int64_t stored32 = A->usym ? stored : (stored + 3) / 4 * 4;   // FP32 half: no grouping
-        const size_t b_val32 = f32 ? align_up(sizeof(float) * (size_t)rows * stored32, 256) : 0;
-        e = hipMalloc(&A->mem_vals, b_uoff + b_val + b_val32);
-        if (e != hipSuccess) return fail_union(hip_fail(e, "hipMalloc(matrix values)"));
-        char* mv = static_cast<char*>(A->mem_vals);
-        A->uoff = reinterpret_cast<int32_t*>(mv);
-        A->sval = reinterpret_cast<double*>(mv + b_uoff);
-        A->sval32 = f32 ? reinterpret_cast<float*>(mv + b_uoff + b_val) : nullptr;
-        A->mem_bytes = b_small + b_uoff + b_val + b_val32;
+        A->slots = L.slots;
+        A->uoff = reinterpret_cast<int32_t*>(base + L.uoff);
+        A->sval = reinterpret_cast<double*>(base + L.val);
+        A->sval32 = (flags & SSPCG_MATRIX_FP32) ? reinterpret_cast<float*>(base + L.val32) : nullptr;
         std::copy(plan.uoff.begin(), plan.uoff.end(), A->uoff_host);
-        plan_lds(A);
-        e = hipMemcpyAsync(A->uoff, plan.uoff.data(), sizeof(int32_t) * plan.uoff.size(),
-                           hipMemcpyHostToDevice, st);
-        if (e != hipSuccess) return fail_union(hip_fail(e, "offsets"));
-        e = hipFreeAsync(d_union, st);
-        d_union = nullptr;
-        if (e != hipSuccess) return fail(hip_fail(e, "hipFreeAsync"));
-        rc = matrix_fill(A, val, false, st);
-        if (rc != SSPCG_OK) return fail(rc);
-        *out = A;
-        return SSPCG_OK;
+        plan_lds(A.get());
+        SSPCG_HIP(hipMemcpyAsync(A->uoff, plan.uoff.data(), sizeof(int32_t) * plan.uoff.size(),
+                                 hipMemcpyHostToDevice, st));
+    } else {
+        A->slice_ptr = reinterpret_cast<int64_t*>(base + L.slice_ptr);
+        A->slice_aux = reinterpret_cast<int64_t*>(base + L.slice_aux);
+        A->scol = reinterpret_cast<int32_t*>(base + L.col);
+        A->soff = reinterpret_cast<int32_t*>(base + L.soff);
+        A->sval = reinterpret_cast<double*>(base + L.val);
+        A->sval32 = (flags & SSPCG_MATRIX_FP32) ? reinterpret_cast<float*>(base + L.val32) : nullptr;
+        SSPCG_HIP(hipMemcpyAsync(A->slice_ptr, plan.slice_ptr.data(),
+                                 sizeof(int64_t) * plan.slice_ptr.size(), hipMemcpyHostToDevice, st));
+        SSPCG_HIP(hipMemcpyAsync(A->slice_aux, plan.slice_aux.data(),
+                                 sizeof(int64_t) * plan.slice_aux.size(), hipMemcpyHostToDevice, st));
+        RETURN_IF(matrix_pack(A.get(), st));
     }
-    const size_t b_col = align_up(sizeof(int32_t) * (size_t)plan.ncol, 256);
-    const size_t b_off = align_up(sizeof(int32_t) * (size_t)plan.nsoff, 256);
-    const size_t b_val = align_up(sizeof(double) * (size_t)A->slots, 256);
-    const size_t b_val32 = f32 ? align_up(sizeof(float) * (size_t)A->slots, 256) : 0;
-    e = hipMalloc(&A->mem_vals, b_col + b_off + b_val + b_val32);
-    if (e != hipSuccess) return fail_union(hip_fail(e, "hipMalloc(matrix values)"));
-    char* mv = static_cast<char*>(A->mem_vals);
-    A->scol = reinterpret_cast<int32_t*>(mv);
-    A->soff = reinterpret_cast<int32_t*>(mv + b_col);
-    A->sval = reinterpret_cast<double*>(mv + b_col + b_off);
-    A->sval32 = f32 ? reinterpret_cast<float*>(mv + b_col + b_off + b_val) : nullptr;
-    A->mem_bytes = b_small + b_col + b_off + b_val + b_val32;
-    e = hipMemcpyAsync(A->slice_ptr, plan.slice_ptr.data(), sizeof(int64_t) * plan.slice_ptr.size(),
-                       hipMemcpyHostToDevice, st);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(A->slice_aux, plan.slice_aux.data(),
-                           sizeof(int64_t) * plan.slice_aux.size(), hipMemcpyHostToDevice, st);
-    if (e != hipSuccess) return fail_union(hip_fail(e, "slice offsets"));
-    rc = matrix_pack(A, d_union, st);
-    if (rc != SSPCG_OK) return fail_union(rc);
-    e = hipFreeAsync(d_union, st);
-    d_union = nullptr;
-    if (e != hipSuccess) return fail(hip_fail(e, "hipFreeAsync"));
-    rc = matrix_fill(A, val, false, st);
-    if (rc != SSPCG_OK) return fail(rc);
-    *out = A;
+    RETURN_IF(matrix_fill(A.get(), val, false, st));
+    *out = A.release();
     return SSPCG_OK;
     API_CATCH
 }
@@ -902,10 +1009,6 @@ int sspcg_matrix_update_values(sspcg_matrix* A, const double* val, sspcg_stream 
 int sspcg_matrix_destroy(sspcg_matrix* A)
 {
     API_TRY
-    if (!A) return SSPCG_OK;
-    if (A->mem) (void)hipFree(A->mem);
-    if (A->mem_vals) (void)hipFree(A->mem_vals);
-    if (A->host_ctrl) (void)hipHostFree(A->host_ctrl);
     delete A;
     return SSPCG_OK;
     API_CATCH
@@ -922,7 +1025,7 @@ int sspcg_matrix_info(const sspcg_matrix* A, int64_t* n, int64_t* nnz, int64_t* 
     if (slots) *slots = A->slots;
     if (slices) *slices = A->nslices;
     if (shared_slices) *shared_slices = A->nshared;
-    if (device_bytes) *device_bytes = (int64_t)A->mem_bytes;
+    if (device_bytes) *device_bytes = (int64_t)A->aux_used;
     return SSPCG_OK;
 }
 
@@ -939,8 +1042,8 @@ int sspcg_workspace_bytes(const sspcg_matrix* A, const sspcg_params* p, size_t* 
 }
 
 int sspcg_solve(const sspcg_matrix* A, const double* b, double* x, const sspcg_params* p,
-                void* work, size_t work_bytes, sspcg_stream stream, sspcg_result* res,
-                double* history)
+                void* work, size_t work_bytes, void* poll, sspcg_stream stream,
+                sspcg_result* res, double* history, sspcg_profile* profile)
 {
     API_TRY
     RETURN_IF(check_matrix(A));
@@ -950,6 +1053,7 @@ int sspcg_solve(const sspcg_matrix* A, const double* b, double* x, const sspcg_p
     RETURN_IF(check_vec(x, SSPCG_F64, "x"));
     RETURN_IF(check_params(A, p, false));
     if (!work || !aligned(work, 256)) return arg_error("work is NULL or not 256-byte aligned");
+    RETURN_IF(check_poll(poll));
     const Workspace w = layout_sspcg(A->n, p);
     if (work_bytes < w.total) {
         set_error("workspace too small");
@@ -957,23 +1061,18 @@ int sspcg_solve(const sspcg_matrix* A, const double* b, double* x, const sspcg_p
     }
     hipStream_t st = as_stream(stream);
     char* base = static_cast<char*>(work);
-    if (p->profile) std::memset(const_cast<sspcg_profile*>(&A->profile), 0, sizeof(sspcg_profile));
-    if (p->precision == SSPCG_MIXED) return solve_mixed(A, b, x, p, w, base, st, res, history);
-    return solve_fp64(A, b, x, p, w, base, st, res, history);
+    Ctrl* hctrl = static_cast<Ctrl*>(poll);
+    sspcg_profile* prof = p->profile ? profile : nullptr;
+    if (prof) std::memset(prof, 0, sizeof(*prof));
+    if (p->precision == SSPCG_MIXED)
+        return solve_mixed(A, b, x, p, w, base, hctrl, st, res, history, prof);
+    return solve_fp64(A, b, x, p, w, base, hctrl, st, res, history, prof);
     API_CATCH
 }
 
-int sspcg_last_profile(const sspcg_matrix* A, sspcg_profile* out)
-{
-    RETURN_IF(check_matrix(A));
-    if (!out) return arg_error("out is NULL");
-    *out = A->profile;
-    return SSPCG_OK;
-}
-
 int sspcg_pcg_solve(const sspcg_matrix* A, const double* b, double* x, const sspcg_params* p,
-                    void* work, size_t work_bytes, sspcg_stream stream, sspcg_result* res,
-                    double* history)
+                    void* work, size_t work_bytes, void* poll, sspcg_stream stream,
+                    sspcg_result* res, double* history)
 {
     API_TRY
     RETURN_IF(check_matrix(A));
@@ -983,12 +1082,14 @@ int sspcg_pcg_solve(const sspcg_matrix* A, const double* b, double* x, const ssp
     RETURN_IF(check_vec(x, SSPCG_F64, "x"));
     RETURN_IF(check_params(A, p, true));
     if (!work || !aligned(work, 256)) return arg_error("work is NULL or not 256-byte aligned");
+    RETURN_IF(check_poll(poll));
     const Workspace w = layout_pcg(A->n, p);
     if (work_bytes < w.total) {
         set_error("workspace too small");
         return res->status = SSPCG_ERR_WORKSPACE;
     }
-    return solve_pcg(A, b, x, p, w, static_cast<char*>(work), as_stream(stream), res, history);
+    return solve_pcg(A, b, x, p, w, static_cast<char*>(work), static_cast<Ctrl*>(poll),
+                     as_stream(stream), res, history);
     API_CATCH
 }
 

@@ -18,6 +18,9 @@ constexpr int kFinBlock = 1024;    // threads of the single-block finishing kern
 constexpr int kNumXcd = 8;         // accelerator complex dies of an MI355X
 constexpr int kMaxGrid = 4096;     // upper bound on blocks of persistent kernels
 constexpr int kMaxPartials = SSPCG_MAX_S * SSPCG_MAX_S + SSPCG_MAX_S;  // values per block
+// Doubles per outer iteration in the device history of the s-step solve:
+// relres, eta_alpha, eta_beta, conjugacy defect ||B2 - W beta||_F.
+constexpr int kHistStride = 4;
 
 // Device-side control block of a running solve.  Kernels of the outer loop
 // read `done` on entry and return at once when it is set, so the host can

@@ -115,10 +115,11 @@ __device__ inline void solve_column(const double (&W)[S][S], const double (&L)[S
     for (int i = 0; i < S; ++i) X[i][c] = x[i];
 }
 
-// ||B - W X||_F / ||B||_F over nrhs columns (W mirrored from its lower part).
+// ||B - W X||_F and ||B||_F over nrhs columns (W mirrored from its lower part).
 template <int S>
-__device__ inline double reduced_relres(const double (&W)[S][S], const double (&B)[S][S],
-                                        const double (&X)[S][S], int nrhs)
+__device__ inline void reduced_residual(const double (&W)[S][S], const double (&B)[S][S],
+                                        const double (&X)[S][S], int nrhs, double* res,
+                                        double* rhs)
 {
     double num = 0.0, den = 0.0;
     for (int c = 0; c < nrhs; ++c)
@@ -128,7 +129,8 @@ __device__ inline double reduced_relres(const double (&W)[S][S], const double (&
             num += t * t;
             den += B[i][c] * B[i][c];
         }
-    return den > 0.0 ? sqrt(num / den) : 0.0;
+    *res = sqrt(num);
+    *rhs = sqrt(den);
 }
 
 // which = 0: alpha system.  Partials: W lower (row-major, i >= j) then b1.
@@ -192,11 +194,21 @@ __global__ __launch_bounds__(kFinBlock) void k_fgs_step(int which, const double*
                 out[i] = X[i][0];
                 for (int j = 0; j < S; ++j) Wbuf[i * S + j] = W[i][j];
             }
-            if (hist) hist[3 * ctrl->iter + 1] = reduced_relres<S>(W, B, X, 1);
+            if (hist) {
+                double res, rhs;
+                reduced_residual<S>(W, B, X, 1, &res, &rhs);
+                hist[kHistStride * ctrl->iter + 1] = rhs > 0.0 ? res / rhs : 0.0;
+            }
         } else {
             for (int i = 0; i < S; ++i)
                 for (int j = 0; j < S; ++j) out[i * S + j] = X[i][j];
-            if (hist && ctrl->iter > 0) hist[3 * (ctrl->iter - 1) + 2] = reduced_relres<S>(W, B, X, S);
+            if (hist && ctrl->iter > 0) {
+                // eta_beta and the conjugacy defect: Q_{k+1}^T A Q_k = -(B2 - W beta)^T
+                double res, rhs;
+                reduced_residual<S>(W, B, X, S, &res, &rhs);
+                hist[kHistStride * (ctrl->iter - 1) + 2] = rhs > 0.0 ? res / rhs : 0.0;
+                hist[kHistStride * (ctrl->iter - 1) + 3] = res;
+            }
         }
     }
 }
@@ -258,7 +270,11 @@ __global__ __launch_bounds__(kWave) void k_norm_step(const double* __restrict__ 
     const double relres = sqrt(rr) / ctrl->nb;
     ctrl->relres = relres;
     ctrl->iter = (int32_t)(k + 1);
-    if (hist) hist[3 * k] = relres;
+    if (hist) {
+        hist[kHistStride * k] = relres;
+        hist[kHistStride * k + 2] = 0.0;
+        hist[kHistStride * k + 3] = 0.0;
+    }
     if (!isfinite(relres)) {
         ctrl->status = SSPCG_ERR_NONFINITE;
         ctrl->done = 1;

@@ -10,13 +10,14 @@ struct sspcg_matrix {
     const int32_t* row_ptr = nullptr;   // caller's CSR (device, not owned)
     const int32_t* col = nullptr;
     int64_t nslices = 0, slots = 0, nshared = 0;
-    int64_t* slice_ptr = nullptr;       // owned (inside `mem`)
-    int64_t* slice_aux = nullptr;       // owned (inside `mem`)
-    int32_t* scol = nullptr;            // owned (inside `mem_vals`)
-    int32_t* soff = nullptr;            // owned (inside `mem_vals`)
+    // Every device array below lives in the caller's `aux` buffer.
+    int64_t* slice_ptr = nullptr;
+    int64_t* slice_aux = nullptr;
+    int32_t* scol = nullptr;
+    int32_t* soff = nullptr;
     int32_t uniform = 0, uw = 0;        // uniform layout: global offset list length
     int32_t usym = 0;                   // uniform layout: symmetric half storage
-    int32_t* uoff = nullptr;            // owned (inside `mem_vals`)
+    int32_t* uoff = nullptr;
     int32_t uoff_host[32] = {};         // the same list, copied into kernel arguments
     int32_t lds_n = 0, ncl = 0, lds_w = 0, lds_self = 0;   // LDS staging of x (see Sell)
     int32_t cl_lo[32] = {}, lds_k[32] = {};
@@ -24,12 +25,14 @@ struct sspcg_matrix {
     float* sval32 = nullptr;
     double* dinv = nullptr;
     float* dinv32 = nullptr;
+    // analysis area (the first bytes of `aux`): check flags, per-slice
+    // longest row, per-slice offset union and its length
     int32_t* dflags = nullptr;
-    void* mem = nullptr;                // device allocation: slice_ptr/aux, dinv, dinv32, dflags
-    void* mem_vals = nullptr;           // device allocation: scol, soff, sval, sval32
-    size_t mem_bytes = 0;
-    sspcg::Ctrl* host_ctrl = nullptr;   // pinned mirror for polling (2 entries)
-    sspcg_profile profile{};            // last profiled solve
+    int32_t* a_width = nullptr;
+    int32_t* a_ulen = nullptr;
+    int32_t* a_union = nullptr;
+    void* aux = nullptr;                // the caller's buffer
+    size_t aux_used = 0;                // bytes of it in use
 };
 
 namespace sspcg {
@@ -39,9 +42,10 @@ Sell<T> sell_view(const sspcg_matrix* A);
 
 // Matrix layout (sell.hip).  inspect validates the CSR input on the device
 // and writes dinv; with a plan it also chooses the kind of every slice (the
-// per-slice offset unions stay in *d_union, nslices x kMaxUnion, for
+// per-slice offset unions stay in the analysis area, A->a_union, for
 // matrix_pack).  pack copies the chosen offset lists; fill writes the
-// sliced values (and explicit columns).
+// sliced values (and explicit columns).  None of them allocates: the
+// analysis area and every output array are set in A beforehand.
 struct LayoutPlan {
     std::vector<int64_t> slice_ptr, slice_aux;
     int64_t slots = 0, ncol = 0, nsoff = 0, nshared = 0;
@@ -51,12 +55,15 @@ struct LayoutPlan {
 // write_dinv = false checks the values without touching the matrix.  With a
 // plan, allow_sym lets the uniform layout use the symmetric half storage.
 int matrix_inspect(sspcg_matrix* A, const double* val, bool values_only, LayoutPlan* plan,
-                   int32_t** d_union, hipStream_t st, bool write_dinv = true,
-                   bool allow_sym = true);
+                   hipStream_t st, bool write_dinv = true, bool allow_sym = true);
+// Bytes of the analysis area for n rows (also the scratch of the size query).
+size_t analysis_bytes(int64_t n);
+// Points A->dflags, a_width, a_ulen, a_union into the area at `base`.
+void bind_analysis(sspcg_matrix* A, void* base);
 // Whether the CSR values val (the matrix's pattern) are symmetric bit for
 // bit: a(i, j) equals a(j, i), an absent entry counting as +0.
 int matrix_check_symmetric(const sspcg_matrix* A, const double* val, bool* sym, hipStream_t st);
-int matrix_pack(sspcg_matrix* A, const int32_t* d_union, hipStream_t st);
+int matrix_pack(sspcg_matrix* A, hipStream_t st);
 int matrix_fill(sspcg_matrix* A, const double* val, bool values_only, hipStream_t st);
 // Windows of the LDS staging of x for the uniform offset list (host only).
 void plan_lds(sspcg_matrix* A);

@@ -1004,25 +1004,41 @@ int matrix_check_symmetric(const sspcg_matrix* A, const double* val, bool* sym, 
     return SSPCG_OK;
 }
 
+static size_t area_align(size_t v) { return (v + 255) / 256 * 256; }
+
+size_t analysis_bytes(int64_t n)
+{
+    const int64_t nslices = (n + kSlice - 1) / kSlice;
+    return 256 + 2 * area_align(sizeof(int32_t) * (size_t)nslices) +
+           area_align(sizeof(int32_t) * (size_t)nslices * kMaxUnion);
+}
+
+void bind_analysis(sspcg_matrix* A, void* base)
+{
+    char* p = static_cast<char*>(base);
+    const size_t per = area_align(sizeof(int32_t) * (size_t)A->nslices);
+    A->dflags = reinterpret_cast<int32_t*>(p);
+    A->a_width = reinterpret_cast<int32_t*>(p + 256);
+    A->a_ulen = reinterpret_cast<int32_t*>(p + 256 + per);
+    A->a_union = reinterpret_cast<int32_t*>(p + 256 + 2 * per);
+}
+
 int matrix_inspect(sspcg_matrix* A, const double* val, bool values_only, LayoutPlan* plan,
-                   int32_t** d_union, hipStream_t st, bool write_dinv, bool allow_sym)
+                   hipStream_t st, bool write_dinv, bool allow_sym)
 {
     const int64_t nrows_padded = A->nslices * kSlice;
     const int blocks = (int)((nrows_padded + kRowBlock - 1) / kRowBlock);
     std::vector<int32_t> width(A->nslices), ulen(A->nslices);
-    int32_t* dwidth = nullptr;
-    int32_t* dulen = nullptr;
-    SSPCG_HIP(hipMallocAsync((void**)&dwidth, sizeof(int32_t) * A->nslices, st));
     SSPCG_HIP(hipMemsetAsync(A->dflags, 0, sizeof(int32_t), st));
     hipLaunchKernelGGL(k_inspect, dim3(blocks), dim3(kRowBlock), 0, st, A->n, A->nnz, A->nslices,
-                       A->row_ptr, A->col, val, A->dflags, dwidth, write_dinv ? A->dinv : nullptr,
-                       write_dinv ? A->dinv32 : nullptr, values_only);
+                       A->row_ptr, A->col, val, A->dflags, A->a_width,
+                       write_dinv ? A->dinv : nullptr, write_dinv ? A->dinv32 : nullptr,
+                       values_only);
     SSPCG_LAUNCHED("k_inspect");
     int32_t hflags = 0;
     SSPCG_HIP(hipMemcpyAsync(&hflags, A->dflags, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    SSPCG_HIP(hipMemcpyAsync(width.data(), dwidth, sizeof(int32_t) * A->nslices,
+    SSPCG_HIP(hipMemcpyAsync(width.data(), A->a_width, sizeof(int32_t) * A->nslices,
                              hipMemcpyDeviceToHost, st));
-    SSPCG_HIP(hipFreeAsync(dwidth, st));
     SSPCG_HIP(hipStreamSynchronize(st));
     if (hflags & kFlagPattern) {
         set_error("malformed CSR pattern (row pointers or column indices)");
@@ -1038,14 +1054,11 @@ int matrix_inspect(sspcg_matrix* A, const double* val, bool values_only, LayoutP
     }
     if (!plan) return SSPCG_OK;
     // the pattern is valid: choose the kind of every slice
-    SSPCG_HIP(hipMallocAsync((void**)d_union, sizeof(int32_t) * A->nslices * kMaxUnion, st));
-    SSPCG_HIP(hipMallocAsync((void**)&dulen, sizeof(int32_t) * A->nslices, st));
     hipLaunchKernelGGL(k_slice_union, dim3(blocks), dim3(kRowBlock), 0, st, A->n, A->nslices,
-                       A->row_ptr, A->col, *d_union, dulen);
+                       A->row_ptr, A->col, A->a_union, A->a_ulen);
     SSPCG_LAUNCHED("k_slice_union");
-    SSPCG_HIP(hipMemcpyAsync(ulen.data(), dulen, sizeof(int32_t) * A->nslices,
+    SSPCG_HIP(hipMemcpyAsync(ulen.data(), A->a_ulen, sizeof(int32_t) * A->nslices,
                              hipMemcpyDeviceToHost, st));
-    SSPCG_HIP(hipFreeAsync(dulen, st));
     SSPCG_HIP(hipStreamSynchronize(st));
     plan->slice_ptr.assign(A->nslices + 1, 0);
     plan->slice_aux.assign(A->nslices, 0);
@@ -1075,8 +1088,9 @@ int matrix_inspect(sspcg_matrix* A, const double* val, bool values_only, LayoutP
     plan->usym = false;
     if (plan->nshared == A->nslices) {
         std::vector<int32_t> hun((size_t)A->nslices * kMaxUnion);
-        SSPCG_HIP(hipMemcpy(hun.data(), *d_union, sizeof(int32_t) * hun.size(),
-                            hipMemcpyDeviceToHost));
+        SSPCG_HIP(hipMemcpyAsync(hun.data(), A->a_union, sizeof(int32_t) * hun.size(),
+                                 hipMemcpyDeviceToHost, st));
+        SSPCG_HIP(hipStreamSynchronize(st));
         std::vector<int32_t> all;
         all.reserve(64);
         bool fits = true;
@@ -1112,11 +1126,11 @@ int matrix_inspect(sspcg_matrix* A, const double* val, bool values_only, LayoutP
     return SSPCG_OK;
 }
 
-int matrix_pack(sspcg_matrix* A, const int32_t* d_union, hipStream_t st)
+int matrix_pack(sspcg_matrix* A, hipStream_t st)
 {
     const int blocks = (int)((A->nslices * kSlice + kRowBlock - 1) / kRowBlock);
     hipLaunchKernelGGL(k_pack_union, dim3(blocks), dim3(kRowBlock), 0, st, A->nslices,
-                       A->slice_ptr, A->slice_aux, d_union, A->soff);
+                       A->slice_ptr, A->slice_aux, A->a_union, A->soff);
     SSPCG_LAUNCHED("k_pack_union");
     return SSPCG_OK;
 }

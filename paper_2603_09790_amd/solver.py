@@ -50,19 +50,27 @@ def _on(t: torch.Tensor, device, dtype=None) -> torch.Tensor:
     return t.to(device=device, dtype=dtype or t.dtype).contiguous()
 
 
+def _bytes(nbytes: int, device) -> torch.Tensor:
+    """A device buffer of nbytes (torch's allocations are 256-byte aligned)."""
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
 class Matrix:
     """The library's copy of a CSR matrix on one GPU.
 
     row_ptr / col / val may be numpy arrays or tensors; they are copied to the
-    device and kept alive for the handle's lifetime.  ``fp32=True`` also keeps
-    FP32 values, which the mixed-precision solve and FP32 kernels need.  A
-    symmetric stencil matrix is stored as one triangle unless
-    ``full_storage=True`` (needed to update it later with non-symmetric values).
+    device and kept alive for the handle's lifetime, as is the tensor `aux`
+    that holds the library's layout (its size comes from
+    sspcg_matrix_aux_bytes).  ``fp32=True`` also keeps FP32 values, which the
+    mixed-precision solve and FP32 kernels need.  A symmetric stencil matrix
+    is stored as one triangle unless ``full_storage=True`` (needed to update
+    it later with non-symmetric values).
     """
 
     def __init__(self, row_ptr, col, val, *, fp32: bool = False, full_storage: bool = False,
                  device=None):
         self.device = _dev(device)
+        self.handle = None
         with torch.cuda.device(self.device):
             self.row_ptr = _on(row_ptr, self.device, torch.int32)
             self.col = _on(col, self.device, torch.int32)
@@ -70,14 +78,23 @@ class Matrix:
             self.n = self.row_ptr.numel() - 1
             self.nnz = self.col.numel()
             self.fp32 = fp32
-            h = ctypes.c_void_p()
             flags = (L.MATRIX_FP32 if fp32 else 0) | (L.MATRIX_FULL_STORAGE if full_storage else 0)
-            st = L.lib().sspcg_matrix_create(self.n, self.nnz, _p(self.row_ptr), _p(self.col),
-                                             _p(self.val), flags, _stream(self.device),
-                                             ctypes.byref(h))
-            L.check(st, "sspcg_matrix_create")
+            lib = L.lib()
+            args = (self.n, self.nnz, _p(self.row_ptr), _p(self.col), _p(self.val), flags)
+            scratch = _bytes(lib.sspcg_matrix_scratch_bytes(max(self.n, 1)), self.device)
+            need = ctypes.c_size_t()
+            L.check(lib.sspcg_matrix_aux_bytes(*args, _p(scratch), scratch.numel(),
+                                               _stream(self.device), ctypes.byref(need)),
+                    "sspcg_matrix_aux_bytes")
+            del scratch
+            self.aux = _bytes(need.value, self.device)
+            h = ctypes.c_void_p()
+            L.check(lib.sspcg_matrix_create(*args, _p(self.aux), self.aux.numel(),
+                                            _stream(self.device), ctypes.byref(h)),
+                    "sspcg_matrix_create")
         self.handle = h
         self._work = None
+        self._poll = None
         self.values_tag = None
 
     @classmethod
@@ -105,8 +122,14 @@ class Matrix:
     def workspace(self, nbytes: int) -> torch.Tensor:
         if self._work is None or self._work.numel() < nbytes:
             self._work = None
-            self._work = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            self._work = _bytes(nbytes, self.device)
         return self._work
+
+    def poll_buffer(self) -> torch.Tensor:
+        """Pinned host buffer the solvers poll the device through."""
+        if self._poll is None:
+            self._poll = torch.empty(L.POLL_BYTES, dtype=torch.uint8, pin_memory=True)
+        return self._poll
 
     def close(self) -> None:
         if getattr(self, "handle", None) is not None and self.handle.value:
@@ -144,7 +167,8 @@ def _params(s, sweeps, interval, tol, precision, gram, max_outer, inner_tol, max
 
 def _result(res: L.Result, st: int) -> dict:
     return dict(status=st, status_name=L.status_string(st), outer_iters=res.outer_iters,
-                refinements=res.refinements, relres=res.relres, device_ms=res.device_ms)
+                refinements=res.refinements, inner_iters_total=res.inner_iters_total,
+                relres=res.relres, relres_true=res.relres_true, device_ms=res.device_ms)
 
 
 def solve(A: Matrix, b: torch.Tensor, x0: torch.Tensor | None = None, *, s: int = 4,
@@ -156,9 +180,11 @@ def solve(A: Matrix, b: torch.Tensor, x0: torch.Tensor | None = None, *, s: int 
     """s-step PCG (Algorithm 1) on A x = b.  Returns (x, info).
 
     info['history'] (when history=True): per outer iteration
-    [relres, eta_alpha, eta_beta] (fp64), or the true relative residual per
-    refinement (mixed).  info['profile'] (when profile=True): GPU time and
-    launches per phase, from HIP events around every phase.
+    [relres, eta_alpha, eta_beta, conjugacy defect ||B2 - W beta||_F] (fp64),
+    or the true relative residual per refinement (mixed).  info['profile']
+    (when profile=True): GPU time and launches per phase, from HIP events
+    around every phase.  info['relres_true']: ||b - A x|| / ||b|| of the
+    returned x, recomputed in FP64 on the device.
     """
     p = _params(s, sweeps, interval, tol, precision, gram, max_outer, inner_tol, max_refine,
                 check_every, profile, sweep_tol, basis, graph)
@@ -178,17 +204,18 @@ def solve(A: Matrix, b: torch.Tensor, x0: torch.Tensor | None = None, *, s: int 
             "sspcg_workspace_bytes")
     work = A.workspace(nbytes.value)
     res = L.Result()
-    nh = (p.max_refine + 1) if precision == "mixed" else 3 * p.max_outer
+    nh = (p.max_refine + 1) if precision == "mixed" else L.HIST_STRIDE * p.max_outer
     hist = (ctypes.c_double * nh)() if history else None
+    pr = L.Profile()
+    poll = A.poll_buffer()
     with torch.cuda.device(dev):
         st = L.lib().sspcg_solve(A.handle, _p(b), _p(x), ctypes.byref(p), _p(work),
-                                 work.numel(), _stream(dev), ctypes.byref(res), hist)
+                                 work.numel(), _p(poll), _stream(dev), ctypes.byref(res), hist,
+                                 ctypes.byref(pr))
     if raise_on_error:
         L.check(st, "sspcg_solve", allow=(L.OK, L.NOT_CONVERGED))
     info = _result(res, st)
     if profile:
-        pr = L.Profile()
-        L.check(L.lib().sspcg_last_profile(A.handle, ctypes.byref(pr)), "sspcg_last_profile")
         info["profile"] = pr.as_dict()
     if history:
         import numpy as np
@@ -196,7 +223,8 @@ def solve(A: Matrix, b: torch.Tensor, x0: torch.Tensor | None = None, *, s: int 
         if precision == "mixed":
             info["history"] = h[:res.refinements + 1].copy()
         else:
-            info["history"] = h[:3 * res.outer_iters].reshape(-1, 3).copy()
+            k = L.HIST_STRIDE
+            info["history"] = h[:k * res.outer_iters].reshape(-1, k).copy()
     return x, info
 
 
@@ -215,9 +243,11 @@ def pcg(A: Matrix, b: torch.Tensor, x0: torch.Tensor | None = None, *, tol: floa
     work = A.workspace(nbytes.value)
     res = L.Result()
     hist = (ctypes.c_double * max_iter)() if history else None
+    poll = A.poll_buffer()
     with torch.cuda.device(dev):
         st = L.lib().sspcg_pcg_solve(A.handle, _p(b), _p(x), ctypes.byref(p), _p(work),
-                                     work.numel(), _stream(dev), ctypes.byref(res), hist)
+                                     work.numel(), _p(poll), _stream(dev), ctypes.byref(res),
+                                     hist)
     if raise_on_error:
         L.check(st, "sspcg_pcg_solve", allow=(L.OK, L.NOT_CONVERGED))
     info = _result(res, st)

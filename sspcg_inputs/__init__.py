@@ -24,7 +24,7 @@ Scale"; the variable-coefficient forms generalise it):
 * Random numbers come from numpy's PCG64 ``default_rng(seed)``.  Seeds used
   by the standard workloads: right-hand side 0, coefficient field 1,
   Lanczos start vector 2, log-coefficients theta 3, regression target 4,
-  finite-difference direction 5.
+  finite-difference direction 5, sampled solution indices 6, probe vectors 7.
 """
 from __future__ import annotations
 
@@ -38,7 +38,7 @@ __all__ = [
     "coeff_blocks", "theta_field", "rhs_uniform", "rhs_normal",
     "x_target", "unit_direction", "closed_form_bounds", "start_vector", "lanczos_bounds",
     "power_bounds", "nnz_formula", "jacobi_inverse", "to_scipy",
-    "workload",
+    "workload", "sample_indices", "probe_vectors", "digest",
 ]
 
 SEED_RHS = 0
@@ -47,6 +47,8 @@ SEED_LANCZOS = 2
 SEED_THETA = 3
 SEED_TARGET = 4
 SEED_DIRECTION = 5
+SEED_SAMPLES = 6
+SEED_PROBES = 7
 
 
 @dataclass
@@ -235,6 +237,29 @@ def x_target(n: int, seed: int = SEED_TARGET) -> np.ndarray:
 def unit_direction(n: int, seed: int = SEED_DIRECTION) -> np.ndarray:
     v = np.random.default_rng(seed).normal(0.0, 1.0, size=n)
     return v / np.linalg.norm(v)
+
+
+def sample_indices(n: int, m: int, seed: int = SEED_SAMPLES) -> np.ndarray:
+    """m distinct row indices in [0, n), sorted (where a solution is sampled)."""
+    m = min(m, n)
+    idx = np.random.default_rng(seed).choice(n, size=m, replace=False)
+    return np.sort(idx).astype(np.int64)
+
+
+def probe_vectors(n: int, k: int, seed: int = SEED_PROBES) -> np.ndarray:
+    """k vectors with N(0,1) entries, shape (k, n): a solution is summarised
+    by its inner products with them."""
+    return np.random.default_rng(seed).normal(0.0, 1.0, size=(k, n))
+
+
+def digest(*arrays) -> str:
+    """SHA-1 of the bytes of the arrays, to tell whether two machines built
+    the same inputs."""
+    import hashlib
+    h = hashlib.sha1()
+    for a in arrays:
+        h.update(np.ascontiguousarray(a).tobytes())
+    return h.hexdigest()
 
 
 def jacobi_inverse(A: CSR) -> np.ndarray:

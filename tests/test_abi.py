@@ -41,9 +41,12 @@ def test_struct_layouts_match_header():
 #include <stdio.h>
 #include "sspcg.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu %zu\n", sizeof(sspcg_params), offsetof(sspcg_params, inner_tol),
-         offsetof(sspcg_params, check_every), offsetof(sspcg_params, basis), sizeof(sspcg_result),
-         offsetof(sspcg_result, relres), offsetof(sspcg_result, device_ms));
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %d\n", sizeof(sspcg_params),
+         offsetof(sspcg_params, inner_tol), offsetof(sspcg_params, check_every),
+         offsetof(sspcg_params, basis), sizeof(sspcg_result),
+         offsetof(sspcg_result, inner_iters_total), offsetof(sspcg_result, relres),
+         offsetof(sspcg_result, relres_true), offsetof(sspcg_result, device_ms),
+         sizeof(sspcg_profile), SSPCG_POLL_BYTES);
   return 0;
 }
 '''
@@ -57,7 +60,9 @@ int main(void) {
                                             check=True).stdout.split()))
     assert vals == [ctypes.sizeof(L.Params), L.Params.inner_tol.offset,
                     L.Params.check_every.offset, L.Params.basis.offset, ctypes.sizeof(L.Result),
-                    L.Result.relres.offset, L.Result.device_ms.offset]
+                    L.Result.inner_iters_total.offset, L.Result.relres.offset,
+                    L.Result.relres_true.offset, L.Result.device_ms.offset,
+                    ctypes.sizeof(L.Profile), L.POLL_BYTES]
 
 
 def test_version_status_defaults():
@@ -72,24 +77,79 @@ def test_version_status_defaults():
     assert (p.s, p.sweeps, p.tol, p.max_outer, p.check_every) == (4, 2, 1e-8, 20000, 8)
 
 
-def test_host_side_argument_errors():
+def test_matrix_memory_queries():
+    """The matrix's device memory is the caller's: a closed-form scratch size
+    for the analysis, then the exact aux size (argument errors are caught on
+    the host, before any HIP call)."""
     lib = P.lib()
+    # analysis area: a flag word, per 64-row slice its longest row, its
+    # offset-union length and a union of up to 32 offsets (int32 each)
+    for n in (1, 64, 65, 4096, 7077888):
+        slices = (n + 63) // 64
+        per = (4 * slices + 255) // 256 * 256
+        assert lib.sspcg_matrix_scratch_bytes(n) == 256 + 2 * per + (128 * slices + 255) // 256 * 256
+    sz = ctypes.c_size_t(123)
+    A = ctypes.c_void_p(256)
+    scratch = ctypes.c_void_p(4096)
+    assert lib.sspcg_matrix_aux_bytes(0, 0, None, None, None, 0, scratch, 1 << 20, None,
+                                      ctypes.byref(sz)) == L.ERR_ARG
+    assert sz.value == 0
+    assert lib.sspcg_matrix_aux_bytes(4, 4, A, A, A, 0, scratch, 1 << 20, None, None) == L.ERR_ARG
+    assert lib.sspcg_matrix_aux_bytes(4, 4, A, A, A, 0, None, 1 << 20, None,
+                                      ctypes.byref(sz)) == L.ERR_ARG
+    assert lib.sspcg_matrix_aux_bytes(4, 4, A, A, A, 0, ctypes.c_void_p(4100), 1 << 20, None,
+                                      ctypes.byref(sz)) == L.ERR_ARG
+    assert lib.sspcg_matrix_aux_bytes(4, 4, A, A, A, 0, scratch, 16, None,
+                                      ctypes.byref(sz)) == L.ERR_WORKSPACE
+    assert lib.sspcg_matrix_aux_bytes(4, 4, A, A, A, 8, scratch, 1 << 20, None,
+                                      ctypes.byref(sz)) == L.ERR_ARG
     h = ctypes.c_void_p()
-    assert lib.sspcg_matrix_create(0, 0, None, None, None, 0, None, ctypes.byref(h)) == L.ERR_ARG
-    assert "n >= 1" in L.last_error()
-    assert lib.sspcg_matrix_create(10, 5, ctypes.c_void_p(256), ctypes.c_void_p(256),
-                                   ctypes.c_void_p(256), 0, None, ctypes.byref(h)) == L.ERR_ARG
-    assert lib.sspcg_matrix_create(10, 10, ctypes.c_void_p(258), ctypes.c_void_p(256),
-                                   ctypes.c_void_p(256), 0, None, ctypes.byref(h)) == L.ERR_ARG
-    assert lib.sspcg_matrix_create(4, 4, ctypes.c_void_p(256), ctypes.c_void_p(256),
-                                   ctypes.c_void_p(256), 8, None, ctypes.byref(h)) == L.ERR_ARG
-    assert lib.sspcg_matrix_create(4, 4, None, None, None, 0, None, None) == L.ERR_ARG
+    assert lib.sspcg_matrix_create(4, 4, A, A, A, 0, None, 1 << 20, None,
+                                   ctypes.byref(h)) == L.ERR_ARG
+    assert lib.sspcg_matrix_create(4, 4, A, A, A, 0, ctypes.c_void_p(4100), 1 << 20, None,
+                                   ctypes.byref(h)) == L.ERR_ARG
+    assert lib.sspcg_matrix_create(4, 4, A, A, A, 0, scratch, 16, None,
+                                   ctypes.byref(h)) == L.ERR_WORKSPACE
+    assert h.value is None
+
+
+def test_solvers_need_a_pinned_poll_buffer():
+    """The solvers poll through caller memory: NULL or misaligned is refused
+    before anything is enqueued (the pinned-memory check itself needs a GPU)."""
+    import torch
+    lib = P.lib()
+    if torch.cuda.is_available():
+        pytest.skip("the handle below is fake; the GPU suite covers real solves")
     p = L.Params()
     lib.sspcg_default_params(ctypes.byref(p))
     res = L.Result()
-    assert lib.sspcg_solve(None, None, None, ctypes.byref(p), None, 0, None,
-                           ctypes.byref(res), None) == L.ERR_ARG
-    assert lib.sspcg_pcg_solve(None, None, None, ctypes.byref(p), None, 0, None,
+    assert lib.sspcg_solve(None, None, None, ctypes.byref(p), None, 0, None, None,
+                           ctypes.byref(res), None, None) == L.ERR_ARG
+
+
+def test_host_side_argument_errors():
+    lib = P.lib()
+    h = ctypes.c_void_p()
+    A = ctypes.c_void_p(256)
+    aux = ctypes.c_void_p(4096)
+    assert lib.sspcg_matrix_create(0, 0, None, None, None, 0, aux, 1 << 20, None,
+                                   ctypes.byref(h)) == L.ERR_ARG
+    assert "n >= 1" in L.last_error()
+    assert lib.sspcg_matrix_create(10, 5, A, A, A, 0, aux, 1 << 20, None,
+                                   ctypes.byref(h)) == L.ERR_ARG
+    assert lib.sspcg_matrix_create(10, 10, ctypes.c_void_p(258), A, A, 0, aux, 1 << 20, None,
+                                   ctypes.byref(h)) == L.ERR_ARG
+    assert lib.sspcg_matrix_create(4, 4, A, A, A, 8, aux, 1 << 20, None,
+                                   ctypes.byref(h)) == L.ERR_ARG
+    assert lib.sspcg_matrix_create(4, 4, None, None, None, 0, aux, 1 << 20, None,
+                                   None) == L.ERR_ARG
+    p = L.Params()
+    lib.sspcg_default_params(ctypes.byref(p))
+    res = L.Result()
+    poll = ctypes.c_void_p(4096)
+    assert lib.sspcg_solve(None, None, None, ctypes.byref(p), None, 0, poll, None,
+                           ctypes.byref(res), None, None) == L.ERR_ARG
+    assert lib.sspcg_pcg_solve(None, None, None, ctypes.byref(p), None, 0, poll, None,
                                ctypes.byref(res), None) == L.ERR_ARG
     sz = ctypes.c_size_t()
     assert lib.sspcg_workspace_bytes(None, ctypes.byref(p), ctypes.byref(sz)) == L.ERR_ARG

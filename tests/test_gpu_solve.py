@@ -107,10 +107,13 @@ def test_history_matches_oracle_early(poisson7):
     _, _, ho = oracle.sspcg(w["A"], w["b"], s=4, sweeps=2, interval=w["interval"], tol=1e-30,
                             max_outer=10, history=True)
     h = info["history"]
-    assert h.shape == (10, 3)
+    assert h.shape == (10, 4) and ho.shape == (10, 4)
     assert np.allclose(h[:, 0], ho[:, 0], rtol=1e-9, atol=0)
     assert np.allclose(h[:, 1], ho[:, 1], rtol=1e-6, atol=1e-12)
     assert np.allclose(h[:-1, 2], ho[:-1, 2], rtol=1e-6, atol=1e-12)
+    # conjugacy defect ||B2 - W beta||_F = ||Q_{k+1}^T A Q_k||_F (Sec. 2)
+    assert np.allclose(h[:-1, 3], ho[:-1, 3], rtol=1e-6, atol=0)
+    assert np.all(h[:-1, 3] > 0)
 
 
 @pytest.mark.parametrize("name", ["poisson5", "diffusion27"])

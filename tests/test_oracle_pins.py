@@ -336,12 +336,20 @@ def test_anorm_error_never_increases(sweeps):
 
 
 def test_conjugacy_defect_and_condition_identity():
-    """Q_{k+1}^T A Q_k = -(B2 - W beta)^T, and kappa(A^{1/2} Q)^2 = kappa(W)."""
+    """Q_{k+1}^T A Q_k = -(B2 - W beta)^T, and kappa(A^{1/2} Q)^2 = kappa(W).
+    The oracle's history reports ||Q_{k+1}^T A Q_k||_F as its fourth column."""
     A = si.stencil("7pt", 6, np.exp(si.theta_field(216)))
     b = si.rhs_uniform(A.n)
     M = si.to_scipy(A).toarray()
     lo, hi = si.lanczos_bounds(A)
     _, _, states = trace(A, b, s=4, sweeps=2, interval=(lo, hi), tol=1e-12, max_outer=6)
+    _, _, hist = oracle.sspcg(A, b, s=4, sweeps=2, interval=(lo, hi), tol=1e-12, max_outer=6,
+                              history=True)
+    assert hist.shape == (6, 4)
+    for k in range(5):
+        defect = np.linalg.norm(states[k + 1]["Q"] @ M @ states[k]["Q"].T)
+        assert abs(hist[k, 3] - defect) <= 1e-9 * defect
+        assert abs(hist[k, 2] * np.linalg.norm(states[k]["B2"]) - defect) <= 1e-9 * defect
     lam, V = np.linalg.eigh(M)
     Mh = (V * np.sqrt(lam)) @ V.T
     for k in range(4):
