@@ -57,7 +57,9 @@ def lib():
     global _lib
     if _lib is not None:
         return _lib
-    L = ctypes.CDLL(build())
+    # SSPCG_ORACLE_LIB names another build of the same source (the mutation
+    # tests load copies with a planted mistake this way).
+    L = ctypes.CDLL(os.environ.get("SSPCG_ORACLE_LIB") or build())
     sig = {
         "or_version": (_I, []),
         "or_threads": (_I, []),
@@ -84,6 +86,8 @@ def lib():
         "or_gram_resnorm": (_D, [_I, _I, _P, _P, _P]),
         "or_sspcg": (_I, [_I64, _P, _P, _P, _P, _P, _I, _I, _D, _D, _D, _I, _I, _D, _I, _P, _P]),
         "or_pcg": (_I, [_I64, _P, _P, _P, _P, _P, _D, _I, _P, _P]),
+        "or_inner_sspcg_f32": (_I, [_I64, _P, _P, _P, _P, _P, _P, _I, _I, _D, _D, _D, _I,
+                                    _P]),
         "or_sspcg_mixed": (_I, [_I64, _P, _P, _P, _P, _P, _I, _I, _D, _D, _D, _D, _I, _I,
                                 _P, _P]),
         "or_diffusion7_assemble": (None, [_I64, _P, _P, _P, _P]),
@@ -291,6 +295,18 @@ def sspcg_mixed(A, b, x0=None, *, s, sweeps, interval, tol, inner_tol=1e-4,
     if history:
         return x, out, hist[:out["refinements"] + 1]
     return x, out
+
+
+def inner_sspcg_f32(A, val32, dinv32, r32, *, s, sweeps, interval, inner_tol, max_inner):
+    """The refinement's inner solve: FP32-storage s-step PCG for A d = r32
+    from d = 0.  Returns (d, status, outer iterations)."""
+    val32, dinv32, r32 = _f32(val32), _f32(dinv32), _f32(r32)
+    d = np.empty(A.n, dtype=np.float32)
+    it = ctypes.c_int(0)
+    st = lib().or_inner_sspcg_f32(A.n, _p(A.row_ptr), _p(A.col), _p(val32), _p(dinv32),
+                                  _p(r32), _p(d), s, sweeps, interval[0], interval[1],
+                                  inner_tol, max_inner, ctypes.byref(it))
+    return d, st, it.value
 
 
 def diffusion7_assemble(A, theta) -> np.ndarray:

@@ -709,8 +709,9 @@ void or_block_update_f32(int64_t n, int s, const float* Z, float* Q, const float
 
 /* Inner FP32 s-step PCG for A d = r32 from d = 0; stops when the recursive
  * inner residual satisfies ||r_in|| <= inner_tol * ||r32|| or after
- * max_inner outer iterations.  Returns a status; *iters gets the count. */
-static int inner_sspcg_f32(int64_t n, const int32_t* rp, const int32_t* col,
+ * max_inner outer iterations.  Returns a status; *iters gets the count.
+ * Exported so that tests can pin it directly. */
+int or_inner_sspcg_f32(int64_t n, const int32_t* rp, const int32_t* col,
                            const float* val, const float* dinv, const float* r32,
                            float* d, int s, int sweeps, double lmin, double lmax,
                            double inner_tol, int max_inner, int* iters)
@@ -801,7 +802,7 @@ int or_sspcg_mixed(int64_t n, const int32_t* rp, const int32_t* col, const doubl
         if (itol < inner_tol) itol = inner_tol;
         if (itol > 0.5) itol = 0.5;
         int it = 0;
-        const int st = inner_sspcg_f32(n, rp, col, val32, dinv32, r32, d32, s, sweeps,
+        const int st = or_inner_sspcg_f32(n, rp, col, val32, dinv32, r32, d32, s, sweeps,
                                        lmin, lmax, itol, max_inner, &it);
         inner_total += it;
         if (st != OR_OK && st != OR_NOT_CONVERGED) { status = st; break; }
