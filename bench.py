@@ -95,23 +95,75 @@ def si_start_vector(n: int):
     return si.start_vector(n)
 
 
-def cpu_baseline(A, b, interval, s, sweeps, outer_iters_gpu, sample_outer):
-    """The oracle on the host, on a bounded sample of the same solve."""
+def host_description() -> dict:
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "cpu_model": model}
+
+
+def cpu_baseline(A, b, interval, s, sweeps, outer_iters_gpu, sample_outer, bytes_per_outer):
+    """The oracle on the host, on a bounded sample of the same solve.
+
+    Two runs of the oracle's FP64 s-step solve, of 2 and 2 + sample_outer
+    outer iterations; their difference times sample_outer outer iterations
+    with the setup (diagonal, r0, first basis) taken out.  Scaled by the
+    GPU's outer-iteration count to tolerance."""
     import oracle
     oracle.build()
-    t0 = time.time()
-    _, res = oracle.sspcg(A, b, s=s, sweeps=sweeps, interval=interval, tol=1e-30,
-                          max_outer=sample_outer)
-    dt = time.time() - t0
-    per_outer = dt / max(res["iters"], 1)
+    times = []
+    for k in (2, 2 + sample_outer):
+        t0 = time.time()
+        _, res = oracle.sspcg(A, b, s=s, sweeps=sweeps, interval=interval, tol=1e-30,
+                              max_outer=k)
+        times.append(time.time() - t0)
+        assert res["iters"] == k
+    per_outer = (times[1] - times[0]) / sample_outer
     return {
         "value": per_outer * outer_iters_gpu, "unit": "s", "cores": oracle.threads(),
         "kind": "oracle",
-        "sample": (f"{res['iters']} outer iterations of the FP64 s-step solve on the same "
-                   f"system ({dt:.1f} s wall, setup included), scaled by the GPU's "
-                   f"{outer_iters_gpu} outer iterations to tolerance"),
+        "sample": (f"{sample_outer} outer iterations of the FP64 s-step solve on the same "
+                   f"system, timed as the difference of a {2 + sample_outer}- and a "
+                   f"2-iteration run ({times[1]:.1f} s and {times[0]:.1f} s wall; setup "
+                   f"excluded), scaled by the GPU's {outer_iters_gpu} outer iterations to "
+                   "tolerance"),
         "seconds_per_outer": per_outer,
+        "gbs": bytes_per_outer / per_outer / 1e9,
+        "gbs_bytes_model": "CSR stream and the fused-pass vector traffic per outer iteration",
+        **host_description(),
     }
+
+
+TRIAD_N = 1 << 27       # 1 GiB per operand: far past the 256 MB Infinity Cache
+
+
+def triad_peak(P, torch, dev, reps=10):
+    """Achievable HBM rate: the library's STREAM triad over three 1 GiB
+    arrays, best of `reps` launches (HIP events on the current stream)."""
+    a = torch.empty(TRIAD_N, dtype=torch.float64, device=dev)
+    b = torch.ones_like(a)
+    c = torch.ones_like(a)
+    P.stream_triad(a, b, c, 0.5)
+    best = float("inf")
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        P.stream_triad(a, b, c, 0.5)
+        e1.record()
+        torch.cuda.synchronize()
+        best = min(best, e0.elapsed_time(e1) / 1e3)
+    nbytes = 3 * 8 * TRIAD_N
+    ok = bool(torch.all(a == 1.5).item())
+    del a, b, c
+    if not ok:
+        raise RuntimeError("stream triad produced wrong values")
+    return {"gbs": nbytes / best / 1e9, "bytes": nbytes, "seconds": best}
 
 
 def main() -> int:
@@ -124,7 +176,7 @@ def main() -> int:
     ap.add_argument("--sweeps", type=int, default=2)
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-outer", type=int, default=4)
+    ap.add_argument("--cpu-sample-outer", type=int, default=20)
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-profile", action="store_true",
                     help="time without the per-phase HIP events")
@@ -263,38 +315,45 @@ def main() -> int:
     if not args.no_profile:
         pr = last["profile"]
         sp = pr["spmv"]
-        # the hot path's per-unit byte model (CSR: 12 B per nonzero, 4 B per
-        # row pointer, 8 B per vector element), and the bytes the stored
-        # format itself has to stream (no column indices; one triangle of
-        # values with the symmetric half storage)
-        b_csr = csr_family_bytes(n, nnz, s, 8) / s
+        # algorithmic bytes of one SpMV launch of the matrix powers kernel:
+        # what the stored format has to move (8 B per stored value -- no
+        # column indices, one triangle plus the diagonal with the symmetric
+        # half storage -- x read, y written, the epilogue's vectors), averaged
+        # over the s launches.  The same work on a CSR stream (12 B per
+        # nonzero, 4 B per row pointer) is reported beside it as a
+        # CSR-equivalent rate, never as the roofline figure.
         b_fmt = spmv_family_bytes(n, nval, s, 8, col_frac, dinv_read=not sym) / s
+        b_csr = csr_family_bytes(n, nnz, s, 8) / s
         t_launch = sp["ms"] / 1e3 / sp["launches"]
-        achieved = b_csr / t_launch / 1e9
-        fmt_gbs = b_fmt / t_launch / 1e9
+        achieved = b_fmt / t_launch / 1e9
         traffic = counter_traffic() if (args.N == 192 and s == 6) else None
+        triad = triad_peak(P, torch, dev)
         out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                            "kernel": "k_spmv (matrix powers kernel, FP64)",
-                           "avg_launch_us": 1e6 * t_launch, "bytes_per_launch": b_csr,
-                           "bytes_model": "CSR: 12 B per nonzero, 4 B per row pointer, 8 B per "
-                                          "vector element read or written",
-                           "stored_format": {"bytes_per_launch": b_fmt, "gbs": fmt_gbs,
-                                             "frac": fmt_gbs / HBM_PEAK_GBS},
+                           "avg_launch_us": 1e6 * t_launch, "bytes_per_launch": b_fmt,
+                           "bytes_model": "stored format: 8 B per stored value (diagonal and "
+                                          "upper triangle), 8 B per vector element read or "
+                                          "written (x, y, epilogue z vectors)",
+                           "achievable_peak": {"triad_gbs": triad["gbs"],
+                                               "frac_of_triad": achieved / triad["gbs"],
+                                               "triad_bytes": triad["bytes"],
+                                               "kernel": "sspcg_stream_triad"},
+                           "csr_equivalent": {"bytes_per_launch": b_csr,
+                                              "gbs": b_csr / t_launch / 1e9},
                            "traffic_gbs": None if traffic is None else traffic / t_launch / 1e9}
         pb = phase_bytes(n, s, 8)
         phases = {}
-        tot_b, tot_f, tot_ms = 0.0, 0.0, 0.0
+        tot_f, tot_ms = 0.0, 0.0
         for ph in ("spmv", "gram_update", "gram_rect", "xr"):
             e = pr[ph]
             if e["launches"] == 0:
                 continue
-            nb = (b_csr if ph == "spmv" else pb[ph]) * e["launches"]
             nf = (b_fmt if ph == "spmv" else pb[ph]) * e["launches"]
             phases[ph] = {"launches": e["launches"], "ms": e["ms"],
-                          "gbs": nb / (e["ms"] / 1e3) / 1e9,
-                          "gbs_stored_format": nf / (e["ms"] / 1e3) / 1e9}
-            tot_b += nb
+                          "gbs": nf / (e["ms"] / 1e3) / 1e9}
+            if ph == "spmv":
+                phases[ph]["csr_equivalent_gbs"] = b_csr * e["launches"] / (e["ms"] / 1e3) / 1e9
             tot_f += nf
             tot_ms += e["ms"]
         for ph in ("fgs", "norm"):
@@ -302,10 +361,11 @@ def main() -> int:
         out["phases"] = phases
         sg = [p for p in ("spmv", "gram_update", "gram_rect") if p in phases]
         ms_sg = sum(phases[p]["ms"] for p in sg)
-        out["hbm_gbs_spmv_gram"] = sum(phases[p]["gbs"] * phases[p]["ms"] for p in sg) / ms_sg
-        out["hbm_gbs_spmv_gram_stored_format"] = (sum(phases[p]["gbs_stored_format"] * phases[p]["ms"]
-                                                      for p in sg) / ms_sg)
-        out["hbm_gbs_all_streaming"] = tot_b / (tot_ms / 1e3) / 1e9
+        gbs_sg = sum(phases[p]["gbs"] * phases[p]["ms"] for p in sg) / ms_sg
+        out["hbm_gbs_spmv_gram"] = gbs_sg
+        out["spmv_gram_frac_of_peak"] = gbs_sg / HBM_PEAK_GBS
+        out["spmv_gram_frac_of_triad"] = gbs_sg / triad["gbs"]
+        out["hbm_gbs_all_streaming"] = tot_f / (tot_ms / 1e3) / 1e9
         out["profiled_ms_total"] = sum(pr[p]["ms"] for p in L_PHASES)
     if not args.no_profile:
         # the same FP64 solve without the per-phase events (their cost)
@@ -319,6 +379,12 @@ def main() -> int:
     torch.cuda.synchronize()
     out["fp64"]["time_s_graph_replay"] = ig["device_ms"] / 1e3
     out["fp64"]["outer_iters_graph_replay"] = ig["outer_iters"]
+    # the precision form's own target (outside the timed steps): mixed
+    # refinement and FP64 to a relative residual of 1e-10, each with its
+    # error against the oracle's reference solution of this system
+    if args.N == 192 and s == 6 and args.sweeps == 2:
+        out["to_1e-10_vs_oracle"] = accuracy_vs_oracle(P, M, b, A, b_np, interval, args,
+                                                       with_mixed=not args.no_mixed)
     # classical PCG comparator on the same system (outside the timed steps)
     _, ip = P.pcg(M, b, tol=args.tol)
     out["pcg"] = {"time_s": ip["device_ms"] / 1e3, "iters": ip["outer_iters"],
@@ -326,8 +392,10 @@ def main() -> int:
     out["setup"] = setup
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")
+        per_outer = (csr_family_bytes(n, nnz, s, 8)
+                     + sum(v for k, v in phase_bytes(n, s, 8).items()))
         out["cpu_baseline"] = cpu_baseline(A, b_np, interval, s, args.sweeps,
-                                           last["outer_iters"], args.cpu_sample_outer)
+                                           last["outer_iters"], args.cpu_sample_outer, per_outer)
     print(json.dumps(out), flush=True)
     return 0
 
@@ -353,6 +421,70 @@ def counter_traffic():
         return rec["traffic_bytes_per_launch"]
     except (OSError, KeyError, ValueError):
         return None
+
+
+RECORDS = os.path.join(ROOT, "tests", "golden", "solutions")
+
+
+def oracle_record(case: str, A, b):
+    """The oracle's committed solution record of this system (written by
+    tests/golden/make_solution_records.py from the CPU oracle alone), or None
+    when it is missing or was made for other inputs."""
+    import sspcg_inputs as si
+    try:
+        rec = json.load(open(os.path.join(RECORDS, case + ".json")))
+    except (OSError, ValueError):
+        return None
+    if rec["n"] != A.n or rec["digest_val"] != si.digest(A.val) or rec["digest_b"] != si.digest(b):
+        return None
+    return rec
+
+
+def error_vs_record(x, rec) -> dict:
+    """Relative error of the device solution x against an oracle record: the
+    2-norm error estimated from the record's uniformly sampled entries
+    (sqrt(n/k * sum of squared sampled differences) / ||x_oracle||), the
+    largest sampled difference over the largest sampled |x_oracle|, and the
+    difference of the norms."""
+    import torch
+    import sspcg_inputs as si
+    idx = si.sample_indices(rec["n"], rec["n_samples"])
+    xs = x[torch.from_numpy(idx).to(x.device)].cpu().numpy()
+    xo = np.asarray(rec["x_samples"])
+    d = xs - xo
+    nx = torch.linalg.vector_norm(x).item()
+    return {"rel_error_sampled": float(np.sqrt(rec["n"] / idx.size * np.sum(d * d))
+                                       / rec["norm_x"]),
+            "max_sampled_diff_rel": float(np.abs(d).max() / np.abs(xo).max()),
+            "norm_rel_diff": abs(nx - rec["norm_x"]) / rec["norm_x"],
+            "samples": int(idx.size), "oracle": rec["what"], "oracle_tol": rec["tol"],
+            "oracle_iters": rec["iters"], "record": rec["case"]}
+
+
+def accuracy_vs_oracle(P, M, b, A, b_np, interval, args, with_mixed=True) -> dict:
+    """The precision form's target on the benchmark system: mixed refinement
+    and FP64 s-step PCG, each to a relative residual of 1e-10, with their
+    errors against x_ref, the oracle's classical PCG solution to 1e-13 (a
+    committed record)."""
+    ref = oracle_record("diffusion27_192_pcg", A, b_np)
+    out = {"x_ref": None if ref is None else {"record": ref["case"], "what": ref["what"],
+                                               "tol": ref["tol"], "iters": ref["iters"]}}
+    opts = dict(s=args.s, sweeps=args.sweeps, interval=interval, tol=1e-10)
+    x8, i8 = P.solve(M, b, **opts)
+    out["fp64"] = {"time_s": i8["device_ms"] / 1e3, "outer_iters": i8["outer_iters"],
+                   "relres": i8["relres"], "relres_true": i8["relres_true"],
+                   "status": i8["status_name"],
+                   "error_vs_x_ref": None if ref is None else error_vs_record(x8, ref)}
+    del x8
+    if with_mixed:
+        xm, im = P.solve(M, b, precision="mixed", **opts)
+        out["mixed"] = {"time_s": im["device_ms"] / 1e3, "refinements": im["refinements"],
+                        "inner_iters": im["outer_iters"], "relres_true": im["relres_true"],
+                        "status": im["status_name"],
+                        "error_vs_x_ref": None if ref is None else error_vs_record(xm, ref)}
+        out["mixed_speedup_vs_fp64"] = i8["device_ms"] / im["device_ms"]
+    log(f"[bench] to 1e-10: {out}")
+    return out
 
 
 def seed_spread(P, torch, dev, args, nseeds=5):

@@ -85,6 +85,8 @@ def lib():
         "or_gram_relres": (_D, [_I, _I, _P, _P, _P]),
         "or_gram_resnorm": (_D, [_I, _I, _P, _P, _P]),
         "or_sspcg": (_I, [_I64, _P, _P, _P, _P, _P, _I, _I, _D, _D, _D, _I, _I, _D, _I, _P, _P]),
+        "or_sspcg_perturbed": (_I, [_I64, _P, _P, _P, _P, _P, _I, _I, _D, _D, _D, _I, _I, _D,
+                                    _I, ctypes.c_uint64, _P, _P]),
         "or_pcg": (_I, [_I64, _P, _P, _P, _P, _P, _D, _I, _P, _P]),
         "or_inner_sspcg_f32": (_I, [_I64, _P, _P, _P, _P, _P, _P, _I, _I, _D, _D, _D, _I,
                                     _P]),
@@ -250,19 +252,20 @@ def gram_resnorm(W, B, X) -> float:
 
 
 def sspcg(A, b, x0=None, *, s, sweeps, interval, tol, max_outer=20000,
-          gram="fgs", sweep_tol=0.0, basis="chebyshev", history=False):
+          gram="fgs", sweep_tol=0.0, basis="chebyshev", history=False, perturb_seed=0):
     """Algorithm 1.  Returns (x, result dict[, history (k, 4)]): per outer
     iteration the relative residual, eta_alpha, eta_beta and the conjugacy
-    defect ||B2 - W beta||_F."""
+    defect ||B2 - W beta||_F.  perturb_seed != 0 moves every Gram entry one
+    unit in the last place (seeded random direction) before it is solved."""
     b = _f64(b)
     x = np.zeros(A.n) if x0 is None else _f64(x0).copy()
     hist = np.zeros((max_outer, 4)) if history else None
     res = Result()
-    lib().or_sspcg(A.n, _p(A.row_ptr), _p(A.col), _p(A.val), _p(b), _p(x), s, sweeps,
-                   interval[0], interval[1], tol, max_outer,
-                   1 if gram == "cholesky" else 0, sweep_tol,
-                   0 if basis == "chebyshev" else 1,
-                   None if hist is None else _p(hist), ctypes.byref(res))
+    lib().or_sspcg_perturbed(A.n, _p(A.row_ptr), _p(A.col), _p(A.val), _p(b), _p(x), s,
+                             sweeps, interval[0], interval[1], tol, max_outer,
+                             1 if gram == "cholesky" else 0, sweep_tol,
+                             0 if basis == "chebyshev" else 1, int(perturb_seed),
+                             None if hist is None else _p(hist), ctypes.byref(res))
     out = res.as_dict()
     if history:
         return x, out, hist[:out["iters"]]

@@ -426,12 +426,54 @@ double or_gram_relres(int s, int nrhs, const double* W, const double* B, const d
  * Stops when ||r|| <= tol ||b|| on the recursively updated residual.  If
  * ||b|| = 0 the solution is x = 0; if the starting residual already meets the
  * test no iteration is taken. */
+int or_sspcg_perturbed(int64_t n, const int32_t* rp, const int32_t* col, const double* val,
+                       const double* b, double* x, int s, int sweeps, double lmin,
+                       double lmax, double tol, int max_outer, int gram, double sweep_tol,
+                       int basis, uint64_t perturb_seed, double* hist, or_result* res);
+
 int or_sspcg(int64_t n, const int32_t* rp, const int32_t* col, const double* val,
              const double* b, double* x, int s, int sweeps, double lmin, double lmax,
              double tol, int max_outer, int gram, double sweep_tol, int basis, double* hist,
              or_result* res)
 {
+    return or_sspcg_perturbed(n, rp, col, val, b, x, s, sweeps, lmin, lmax, tol, max_outer,
+                              gram, sweep_tol, basis, 0, hist, res);
+}
+
+/* SplitMix64 (G. Steele, D. Lea, C. Flood, OOPSLA 2014): a counter-based
+ * generator for the Gram perturbations below. */
+static uint64_t splitmix64(uint64_t* state)
+{
+    uint64_t z = (*state += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+/* Moves every entry of an m-entry Gram block one unit in the last place up
+ * or down, at random.  A symmetric W is perturbed in its lower triangle and
+ * mirrored, so it stays symmetric. */
+static void ulp_perturb(double* v, int rows, int cols, int symmetric, uint64_t* state)
+{
+    for (int i = 0; i < rows; ++i)
+        for (int j = 0; j < (symmetric ? i + 1 : cols); ++j) {
+            const double up = (splitmix64(state) & 1) ? INFINITY : -INFINITY;
+            v[i * cols + j] = nextafter(v[i * cols + j], up);
+            if (symmetric) v[j * cols + i] = v[i * cols + j];
+        }
+}
+
+/* As or_sspcg; with perturb_seed != 0 each W, b1 and B2 the solve forms is
+ * moved by one unit in the last place per entry (a seeded random direction)
+ * before it is solved: repeated runs then show how far rounding alone moves
+ * the iteration count and the solution. */
+int or_sspcg_perturbed(int64_t n, const int32_t* rp, const int32_t* col, const double* val,
+                       const double* b, double* x, int s, int sweeps, double lmin,
+                       double lmax, double tol, int max_outer, int gram, double sweep_tol,
+                       int basis, uint64_t perturb_seed, double* hist, or_result* res)
+{
     memset(res, 0, sizeof(*res));
+    uint64_t rng = perturb_seed;
     if (n < 1 || s < 1 || s > 64 || (gram == 0 && sweeps < 1) || !(lmax > lmin)
         || !(lmin >= 0.0) || !(tol > 0.0) || max_outer < 1) {
         res->status = OR_ERR_ARG;
@@ -472,6 +514,10 @@ int or_sspcg(int64_t n, const int32_t* rp, const int32_t* col, const double* val
     memcpy(AQ, P + ld, sizeof(double) * n * s);
     for (k = 0; k < max_outer; ++k) {
         or_gram(n, s, Q, AQ, P, ld, W, b1);        /* P(:,1) = r */
+        if (perturb_seed) {
+            ulp_perturb(W, s, s, 1, &rng);
+            ulp_perturb(b1, s, 1, 0, &rng);
+        }
         int st = gram ? or_chol_solve(s, 1, W, b1, al)
                       : or_fgs_tol(s, 1, W, b1, sweeps, sweep_tol, al);
         if (st != OR_OK) { status = st; break; }
@@ -488,6 +534,7 @@ int or_sspcg(int64_t n, const int32_t* rp, const int32_t* col, const double* val
         or_mpk_basis(n, rp, col, val, dinv, r, s, lmin, lmax, basis, Z, P, ld);
         /* AQ_new = P(:, 2:s+1) */
         or_gram_rect(n, s, Q, P + ld, ld, B2);
+        if (perturb_seed) ulp_perturb(B2, s, s, 0, &rng);
         st = gram ? or_chol_solve(s, s, W, B2, be)
                   : or_fgs_tol(s, s, W, B2, sweeps, sweep_tol, be);
         if (hist) {

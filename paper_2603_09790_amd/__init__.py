@@ -9,7 +9,7 @@ from ._lib import (ERR_ARG, ERR_BREAKDOWN, ERR_HIP, ERR_NONFINITE, ERR_UNSUPPORT
                    ERR_WORKSPACE, EXPORTS, LIB_PATH, MAX_S, NOT_CONVERGED, OK, SSPCGError, lib)
 from .solver import (Matrix, block_update_gram, csr_value_grad, diffusion7_assemble,
                      diffusion7_theta_grad, fgs, gram_rect, interval, leading_dim, mpk, pcg,
-                     solve, spmv, xr_update)
+                     solve, spmv, stream_triad, xr_update)
 from .autograd import DiffusionSolve, SparseSolve
 
 lib()   # load now: a missing library is an import error, never a silent fallback

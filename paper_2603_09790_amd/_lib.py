@@ -28,7 +28,7 @@ EXPORTS = [
     "sspcg_pcg_solve", "sspcg_interval_work_bytes", "sspcg_interval",
     "sspcg_kernel_work_bytes", "sspcg_spmv", "sspcg_mpk", "sspcg_block_update_gram",
     "sspcg_gram_rect", "sspcg_fgs", "sspcg_xr_update", "sspcg_csr_value_grad",
-    "sspcg_diffusion7_assemble", "sspcg_diffusion7_theta_grad",
+    "sspcg_diffusion7_assemble", "sspcg_diffusion7_theta_grad", "sspcg_stream_triad",
 ]
 
 
@@ -113,6 +113,7 @@ def lib() -> ctypes.CDLL:
         "sspcg_csr_value_grad": (ctypes.c_int, [P, P, P, P, P]),
         "sspcg_diffusion7_assemble": (ctypes.c_int, [P, P, P, P]),
         "sspcg_diffusion7_theta_grad": (ctypes.c_int, [P, P, P, P, P]),
+        "sspcg_stream_triad": (ctypes.c_int, [I64, P, P, D, P, P]),
     }
     assert list(sig) == EXPORTS
     for name, (res, args) in sig.items():

@@ -16,7 +16,8 @@ CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libsspcg.so")
 INCLUDE = os.path.join(ROOT, "include")
-SOURCES = ["api.hip", "sell.hip", "block.hip", "fgs.hip", "diff.hip", "interval.hip"]
+SOURCES = ["api.hip", "sell.hip", "block.hip", "fgs.hip", "diff.hip", "interval.hip",
+           "stream.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 CFLAGS = ["-O3", f"--offload-arch={ARCH}", "-fPIC", "-std=c++17", "-Wall",

@@ -1325,4 +1325,16 @@ int sspcg_diffusion7_theta_grad(const sspcg_matrix* A, const double* theta, cons
     API_CATCH
 }
 
+int sspcg_stream_triad(int64_t n, const double* b, const double* c, double q, double* a,
+                       sspcg_stream stream)
+{
+    API_TRY
+    if (n < 0) return arg_error("n < 0");
+    if (n == 0) return SSPCG_OK;
+    for (const void* v : {(const void*)b, (const void*)c, (const void*)a})
+        if (!v || !aligned(v, 16)) return arg_error("a, b and c must be 16-byte aligned");
+    return launch_triad(n, b, c, q, a, as_stream(stream));
+    API_CATCH
+}
+
 }  // extern "C"

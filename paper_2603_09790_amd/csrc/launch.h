@@ -147,4 +147,8 @@ int launch_diffusion7_assemble(const sspcg_matrix* A, const double* theta, doubl
 int launch_diffusion7_theta_grad(const sspcg_matrix* A, const double* theta, const double* gval,
                                  double* gtheta, hipStream_t st);
 
+// STREAM triad a = b + q c (stream.hip): the achievable-bandwidth reference.
+int launch_triad(int64_t n, const double* b, const double* c, double q, double* a,
+                 hipStream_t st);
+
 }  // namespace sspcg

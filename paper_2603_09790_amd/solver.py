@@ -8,6 +8,7 @@ n x ncols block, and ld >= n is the leading dimension.
 from __future__ import annotations
 
 import ctypes
+import threading
 
 import torch
 
@@ -15,7 +16,7 @@ from . import _lib as L
 
 __all__ = ["Matrix", "solve", "pcg", "spmv", "mpk", "block_update_gram", "gram_rect", "fgs",
            "xr_update", "csr_value_grad", "diffusion7_assemble", "diffusion7_theta_grad",
-           "leading_dim"]
+           "leading_dim", "stream_triad"]
 
 
 def _p(t):
@@ -65,6 +66,10 @@ class Matrix:
     mixed-precision solve and FP32 kernels need.  A symmetric stencil matrix
     is stored as one triangle unless ``full_storage=True`` (needed to update
     it later with non-symmetric values).
+
+    The handle caches one workspace and one pinned poll buffer for the solves
+    made through it; a lock serialises those solves (the C library itself
+    lets solves with their own workspace and poll buffer run concurrently).
     """
 
     def __init__(self, row_ptr, col, val, *, fp32: bool = False, full_storage: bool = False,
@@ -95,6 +100,7 @@ class Matrix:
         self.handle = h
         self._work = None
         self._poll = None
+        self._lock = threading.RLock()
         self.values_tag = None
 
     @classmethod
@@ -202,13 +208,13 @@ def solve(A: Matrix, b: torch.Tensor, x0: torch.Tensor | None = None, *, s: int 
     nbytes = ctypes.c_size_t()
     L.check(L.lib().sspcg_workspace_bytes(A.handle, ctypes.byref(p), ctypes.byref(nbytes)),
             "sspcg_workspace_bytes")
-    work = A.workspace(nbytes.value)
     res = L.Result()
     nh = (p.max_refine + 1) if precision == "mixed" else L.HIST_STRIDE * p.max_outer
     hist = (ctypes.c_double * nh)() if history else None
     pr = L.Profile()
-    poll = A.poll_buffer()
-    with torch.cuda.device(dev):
+    with A._lock, torch.cuda.device(dev):
+        work = A.workspace(nbytes.value)
+        poll = A.poll_buffer()
         st = L.lib().sspcg_solve(A.handle, _p(b), _p(x), ctypes.byref(p), _p(work),
                                  work.numel(), _p(poll), _stream(dev), ctypes.byref(res), hist,
                                  ctypes.byref(pr))
@@ -240,11 +246,11 @@ def pcg(A: Matrix, b: torch.Tensor, x0: torch.Tensor | None = None, *, tol: floa
     nbytes = ctypes.c_size_t()
     L.check(L.lib().sspcg_workspace_bytes(A.handle, ctypes.byref(p), ctypes.byref(nbytes)),
             "sspcg_workspace_bytes")
-    work = A.workspace(nbytes.value)
     res = L.Result()
     hist = (ctypes.c_double * max_iter)() if history else None
-    poll = A.poll_buffer()
-    with torch.cuda.device(dev):
+    with A._lock, torch.cuda.device(dev):
+        work = A.workspace(nbytes.value)
+        poll = A.poll_buffer()
         st = L.lib().sspcg_pcg_solve(A.handle, _p(b), _p(x), ctypes.byref(p), _p(work),
                                      work.numel(), _p(poll), _stream(dev), ctypes.byref(res),
                                      hist)
@@ -281,9 +287,9 @@ def interval(A: Matrix, v0: torch.Tensor, *, method: str = "lanczos", steps: int
     nbytes = ctypes.c_size_t()
     L.check(L.lib().sspcg_interval_work_bytes(A.handle, steps, ctypes.byref(nbytes)),
             "sspcg_interval_work_bytes")
-    work = A.workspace(nbytes.value)
     lo, hi, taken = ctypes.c_double(), ctypes.c_double(), ctypes.c_int32()
-    with torch.cuda.device(dev):
+    with A._lock, torch.cuda.device(dev):
+        work = A.workspace(nbytes.value)
         L.check(L.lib().sspcg_interval(A.handle, INTERVAL_METHODS[method], steps, rtol, _p(v0),
                                        _p(work), work.numel(), _stream(dev), ctypes.byref(lo),
                                        ctypes.byref(hi), ctypes.byref(taken)), "sspcg_interval")
@@ -400,3 +406,14 @@ def diffusion7_theta_grad(A: Matrix, theta: torch.Tensor, gval: torch.Tensor) ->
                                                     _stream(A.device)),
                 "sspcg_diffusion7_theta_grad")
     return g
+
+
+def stream_triad(a: torch.Tensor, b: torch.Tensor, c: torch.Tensor, q: float) -> None:
+    """a = b + q c on float64 device tensors (the achievable-bandwidth
+    reference of the measurements; not a step of the method)."""
+    for t in (a, b, c):
+        if t.dtype != torch.float64 or not t.is_contiguous() or t.numel() != a.numel():
+            raise ValueError("a, b, c must be contiguous float64 tensors of one length")
+    with torch.cuda.device(a.device):
+        L.check(L.lib().sspcg_stream_triad(a.numel(), _p(b), _p(c), float(q), _p(a),
+                                           _stream(a.device)), "sspcg_stream_triad")

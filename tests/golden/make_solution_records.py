@@ -7,16 +7,22 @@ host cores):
 
 * the oracle's status, outer iterations and final relative residuals;
 * ||x||_2;
-* x at 2048 indices drawn with ``sspcg_inputs.sample_indices``;
+* x at 2048 indices drawn with ``sspcg_inputs.sample_indices`` (16384 for
+  the 192^3 workload, whose records also stand in for the full solution in
+  the benchmark's error report);
 * x^T v for the 8 vectors of ``sspcg_inputs.probe_vectors``;
 * the basis interval the solve used (exact, as float.hex), and digests of
   the matrix values and the right-hand side, so that a test can tell whether
   it rebuilt the same system.
 
 The s-step records follow Algorithm 1 with Algorithm 2 and FGS Gram solves
-(``oracle.sspcg``) run to a relative residual of 1e-12; the "pcg" records are
+(``oracle.sspcg``) run to a relative residual of 1e-14; the "pcg" records are
 classical Jacobi PCG (``oracle.pcg``) to 1e-13 and serve as the reference
-solution x_ref of the mixed-precision form.  Only ``oracle`` and
+solution x_ref of the mixed-precision form.  Two solves that each reach a
+relative residual tau can differ by up to kappa_2(A) tau; at tau = 1e-12 the
+7-point 128^3 system (kappa_2 about 6.7e3) let the s-step solutions of two
+correct implementations differ by 1.3e-10, so the s-step records go to 1e-14,
+where such pairs agree to about 1e-13.  Only ``oracle`` and
 ``sspcg_inputs`` are used: no value here comes from the GPU library.
 
     python tests/golden/make_solution_records.py --list
@@ -44,7 +50,7 @@ import sspcg_inputs as si  # noqa: E402
 OUT = os.path.join(HERE, "solutions")
 N_SAMPLES = 2048
 N_PROBES = 8
-SSTEP_TOL = 1e-12
+SSTEP_TOL = 1e-14
 PCG_TOL = 1e-13
 
 
@@ -63,8 +69,8 @@ def _cases() -> dict:
     c["poisson7_128_pcg"] = dict(workload="poisson7", N=128, method="pcg")
     # 27-point heterogeneous diffusion 192^3, s = 6, nu = 2
     c["diffusion27_192_s6_nu2"] = dict(workload="diffusion27", N=192, method="sspcg", s=6,
-                                       sweeps=2)
-    c["diffusion27_192_pcg"] = dict(workload="diffusion27", N=192, method="pcg")
+                                       sweeps=2, samples=16384)
+    c["diffusion27_192_pcg"] = dict(workload="diffusion27", N=192, method="pcg", samples=16384)
     return c
 
 
@@ -89,7 +95,7 @@ def make(case: str) -> dict:
         tol = PCG_TOL
         x, res = oracle.pcg(A, b, tol=tol, max_iter=200000)
     seconds = time.time() - t0
-    idx = si.sample_indices(A.n, N_SAMPLES)
+    idx = si.sample_indices(A.n, spec.get("samples", N_SAMPLES))
     V = si.probe_vectors(A.n, N_PROBES)
     rec = dict(
         case=case,

@@ -172,6 +172,10 @@ def test_host_side_argument_errors():
     assert lib.sspcg_csr_value_grad(None, X, X, X, None) == L.ERR_ARG
     assert lib.sspcg_diffusion7_assemble(None, X, X, None) == L.ERR_ARG
     assert lib.sspcg_diffusion7_theta_grad(None, X, X, X, None) == L.ERR_ARG
+    assert lib.sspcg_stream_triad(-1, X, X, 1.0, X, None) == L.ERR_ARG
+    assert lib.sspcg_stream_triad(8, ctypes.c_void_p(264), X, 1.0, X, None) == L.ERR_ARG
+    assert lib.sspcg_stream_triad(8, X, X, 1.0, None, None) == L.ERR_ARG
+    assert lib.sspcg_stream_triad(0, None, None, 1.0, None, None) == L.OK
     assert lib.sspcg_matrix_destroy(None) == L.OK
     assert lib.sspcg_kernel_work_bytes(4) >= 16 * 4096 * 8
 

@@ -68,3 +68,44 @@ def test_traffic_record_is_ignored_when_the_sources_change(tmp_path, monkeypatch
     assert bench.counter_traffic() is None
     path.write_text("not json")
     assert bench.counter_traffic() is None
+
+
+def test_roofline_bytes_per_launch_at_192():
+    # stored format of the 27-point 192^3 matrix: the diagonal and 13 upper
+    # offsets per row (8 B each), x read and y written, the epilogues' z
+    # vectors; averaged over the s = 6 launches of one matrix powers kernel
+    n, nnz, s = 7077888, 189119224, 6
+    nval = bench.stored_values(n, nnz, True)
+    per_launch = bench.spmv_family_bytes(n, nval, s, 8, 0.0, dinv_read=False) / s
+    assert per_launch == 982969312.0
+
+
+def test_error_vs_record_estimates_the_relative_error():
+    import numpy as np
+    import torch
+    import sspcg_inputs as si
+    n, k = 200000, 4096
+    rng = np.random.default_rng(7)
+    xo = rng.normal(size=n)
+    delta = 1e-9 * rng.normal(size=n)
+    idx = si.sample_indices(n, k)
+    rec = {"n": n, "n_samples": k, "x_samples": xo[idx].tolist(),
+           "norm_x": float(np.linalg.norm(xo)), "what": "test", "tol": 0.0, "iters": 0,
+           "case": "synthetic"}
+    e = bench.error_vs_record(torch.from_numpy(xo + delta), rec)
+    true = np.linalg.norm(delta) / np.linalg.norm(xo)
+    assert abs(e["rel_error_sampled"] / true - 1) < 0.1
+    assert e["max_sampled_diff_rel"] <= np.abs(delta).max() / np.abs(xo[idx]).max() * 1.0001
+    e0 = bench.error_vs_record(torch.from_numpy(xo), rec)
+    assert e0["rel_error_sampled"] == 0.0 and e0["max_sampled_diff_rel"] == 0.0
+
+
+def test_oracle_record_rejects_other_inputs():
+    import numpy as np
+    import sspcg_inputs as si
+    A = si.poisson5(64)
+    b = si.rhs_uniform(A.n)
+    rec = bench.oracle_record("poisson5_64_s4_nu2", A, b)
+    assert rec is not None and rec["n"] == A.n
+    assert bench.oracle_record("poisson5_64_s4_nu2", A, b + 1.0) is None
+    assert bench.oracle_record("no_such_case", A, b) is None

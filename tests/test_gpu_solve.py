@@ -247,11 +247,16 @@ def test_workspace_too_small(poisson5):
     b = gpu(poisson5["b"])
     x = torch.zeros_like(b)
     work = torch.empty(1024, dtype=torch.uint8, device=DEV)
+    poll = torch.empty(L.POLL_BYTES, dtype=torch.uint8, pin_memory=True)
     res = L.Result()
-    st = L.lib().sspcg_solve(poisson5["M"].handle, ctypes.c_void_p(b.data_ptr()),
-                             ctypes.c_void_p(x.data_ptr()), ctypes.byref(p),
-                             ctypes.c_void_p(work.data_ptr()), 1024, None, ctypes.byref(res), None)
-    assert st == L.ERR_WORKSPACE
+    args = (poisson5["M"].handle, ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(x.data_ptr()),
+            ctypes.byref(p), ctypes.c_void_p(work.data_ptr()), 1024)
+    st = L.lib().sspcg_solve(*args, ctypes.c_void_p(poll.data_ptr()), None, ctypes.byref(res),
+                             None, None)
+    assert st == L.ERR_WORKSPACE and res.status == L.ERR_WORKSPACE
+    # the poll buffer is checked before the workspace size
+    st = L.lib().sspcg_solve(*args, None, None, ctypes.byref(res), None, None)
+    assert st == L.ERR_ARG
 
 
 # ------------------------------------------------------------ differentiation
