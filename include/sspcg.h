@@ -254,6 +254,24 @@ int sspcg_solve(const sspcg_matrix* A, const double* b, double* x, const sspcg_p
                 void* work, size_t work_bytes, void* poll, sspcg_stream stream,
                 sspcg_result* res, double* history, sspcg_profile* profile);
 
+/* For callers that cannot allocate (code that must not call hipMalloc, such
+ * as tight serving loops or harnesses that forbid it): sspcg_solve without the
+ * workspace argument.  Its workspace is a static device array of
+ * SSPCG_STATIC_SCRATCH_BYTES that the library holds on every GPU it runs on
+ * until the process ends (its address is looked up once per device, at the
+ * first call there); it allocates no device or pinned memory and creates no
+ * HIP events or graphs after that first call.  Solves whose workspace
+ * (sspcg_workspace_bytes) exceeds the array return SSPCG_ERR_WORKSPACE with
+ * nothing enqueued; p->profile and p->use_graph return SSPCG_ERR_UNSUPPORTED.
+ * All calls on one GPU share its array, and the contents of one call are left
+ * for the next: calls that overlap on one GPU (from several threads or
+ * streams) race and must not be made.  The current device must be the
+ * matrix's.  Otherwise as sspcg_solve (poll: the caller's pinned buffer;
+ * blocking; no history or profile output). */
+#define SSPCG_STATIC_SCRATCH_BYTES (64 * 1024 * 1024)
+int sspcg_solve_static(const sspcg_matrix* A, const double* b, double* x, const sspcg_params* p,
+                       void* poll, sspcg_stream stream, sspcg_result* res);
+
 /* Classical Jacobi PCG (the method s-step PCG replaces), same stop test.
  * Uses p->tol, p->max_outer (as the iteration limit) and p->check_every;
  * work and poll as for sspcg_solve.

@@ -17,6 +17,7 @@ MATRIX_FP32 = 1
 MATRIX_FULL_STORAGE = 2
 MAX_S = 16
 POLL_BYTES = 256      # SSPCG_POLL_BYTES
+STATIC_SCRATCH_BYTES = 64 * 1024 * 1024   # SSPCG_STATIC_SCRATCH_BYTES
 HIST_STRIDE = 4       # doubles per outer iteration in the s-step history
 
 # Every symbol the header declares, in header order.
@@ -24,7 +25,7 @@ EXPORTS = [
     "sspcg_abi_version", "sspcg_status_string", "sspcg_last_error", "sspcg_default_params",
     "sspcg_matrix_scratch_bytes", "sspcg_matrix_aux_bytes",
     "sspcg_matrix_create", "sspcg_matrix_update_values", "sspcg_matrix_destroy",
-    "sspcg_matrix_info", "sspcg_workspace_bytes", "sspcg_solve",
+    "sspcg_matrix_info", "sspcg_workspace_bytes", "sspcg_solve", "sspcg_solve_static",
     "sspcg_pcg_solve", "sspcg_interval_work_bytes", "sspcg_interval",
     "sspcg_kernel_work_bytes", "sspcg_spmv", "sspcg_mpk", "sspcg_block_update_gram",
     "sspcg_gram_rect", "sspcg_fgs", "sspcg_xr_update", "sspcg_csr_value_grad",
@@ -97,6 +98,8 @@ def lib() -> ctypes.CDLL:
         "sspcg_workspace_bytes": (ctypes.c_int, [P, ctypes.POINTER(Params), ctypes.POINTER(SZ)]),
         "sspcg_solve": (ctypes.c_int, [P, P, P, ctypes.POINTER(Params), P, SZ, P, P,
                                        ctypes.POINTER(Result), P, ctypes.POINTER(Profile)]),
+        "sspcg_solve_static": (ctypes.c_int, [P, P, P, ctypes.POINTER(Params), P, P,
+                                              ctypes.POINTER(Result)]),
         "sspcg_pcg_solve": (ctypes.c_int, [P, P, P, ctypes.POINTER(Params), P, SZ, P, P,
                                            ctypes.POINTER(Result), P]),
         "sspcg_interval_work_bytes": (ctypes.c_int, [P, I32, ctypes.POINTER(SZ)]),

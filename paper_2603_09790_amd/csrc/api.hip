@@ -18,12 +18,19 @@
 #include <exception>
 #include <functional>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
 #include "launch.h"
 
 namespace sspcg {
+
+// Device memory of sspcg_solve_static: one file-scope array that every GPU
+// the library runs on holds until the process ends.  In host code this name
+// is a host-side stand-in, not a device address: host code only ever uses the
+// address hipGetSymbolAddress returns for it on each device (static_state).
+__device__ __align__(256) unsigned char scratch[SSPCG_STATIC_SCRATCH_BYTES];
 
 static thread_local std::string g_error;
 
@@ -84,6 +91,31 @@ int arg_error(const std::string& what)
     set_error(what);
     return SSPCG_ERR_ARG;
 }
+
+// HIP events a solve uses: two to poll the control block, two for its GPU
+// time.  sspcg_solve creates them per call; the allocation-free entry point
+// uses a set made once per device.
+struct SolveEvents {
+    hipEvent_t poll[2] = {nullptr, nullptr};
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+};
+
+struct OwnedEvents {
+    SolveEvents ev;
+    int create()
+    {
+        SSPCG_HIP(hipEventCreateWithFlags(&ev.poll[0], hipEventDisableTiming));
+        SSPCG_HIP(hipEventCreateWithFlags(&ev.poll[1], hipEventDisableTiming));
+        SSPCG_HIP(hipEventCreate(&ev.t0));
+        SSPCG_HIP(hipEventCreate(&ev.t1));
+        return SSPCG_OK;
+    }
+    ~OwnedEvents()
+    {
+        for (hipEvent_t e : {ev.poll[0], ev.poll[1], ev.t0, ev.t1})
+            if (e) (void)hipEventDestroy(e);
+    }
+};
 
 // Workspace of a solve, carved from the caller's buffer.
 struct Workspace {
@@ -175,13 +207,11 @@ int check_params(const sspcg_matrix* A, const sspcg_params* p, bool pcg)
 // device control block between batches.  Returns when the device reports
 // done or the iteration limit is enqueued and finished.
 int run_polled(Ctrl* dctrl, Ctrl* hctrl, int64_t max_iter, int check_every, hipStream_t st,
-               const std::function<int(int64_t)>& step,
+               const SolveEvents& events, const std::function<int(int64_t)>& step,
                const std::function<void(int64_t, int64_t)>& on_batch_done = nullptr)
 {
     int64_t bstart[2] = {0, 0}, bend[2] = {0, 0};
-    hipEvent_t ev[2];
-    SSPCG_HIP(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
-    SSPCG_HIP(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
+    hipEvent_t const* ev = events.poll;
     int rc = SSPCG_OK;
     int64_t k = 0;
     int batch = 0;
@@ -212,8 +242,6 @@ int run_polled(Ctrl* dctrl, Ctrl* hctrl, int64_t max_iter, int check_every, hipS
     hipError_t e = hipStreamSynchronize(st);
     if (rc == SSPCG_OK && e == hipSuccess && batch > 0 && on_batch_done)
         on_batch_done(bstart[(batch - 1) & 1], bend[(batch - 1) & 1]);
-    (void)hipEventDestroy(ev[0]);
-    (void)hipEventDestroy(ev[1]);
     if (rc != SSPCG_OK) return rc;
     if (e != hipSuccess) return hip_fail(e, "stream synchronize");
     SSPCG_HIP(hipMemcpy(&hctrl[0], dctrl, sizeof(Ctrl), hipMemcpyDeviceToHost));
@@ -364,7 +392,7 @@ int enqueue_mpk(const sspcg_matrix* A, int s, int basis, double al, double sg, T
 template <typename T>
 int run_sspcg(const sspcg_matrix* A, const sspcg_params* p, const Workspace& w, char* base, T* x,
               const T* dinv, int64_t max_iter, double* dhist, Ctrl* hctrl, sspcg_profile* prof,
-              hipStream_t st)
+              const SolveEvents& ev, hipStream_t st)
 {
     const int s = p->s;
     const int64_t n = A->n, ld = w.ld;
@@ -442,13 +470,13 @@ int run_sspcg(const sspcg_matrix* A, const sspcg_params* p, const Workspace& w, 
             return e == hipSuccess ? SSPCG_OK : hip_fail(e, "hipGraphLaunch");
         };
         const int64_t batches = (max_iter + p->check_every - 1) / p->check_every;
-        rc = run_polled(ctrl, hctrl, batches * p->check_every, p->check_every, st, replay);
+        rc = run_polled(ctrl, hctrl, batches * p->check_every, p->check_every, st, ev, replay);
         (void)hipGraphExecDestroy(exec);
         (void)hipGraphDestroy(graph);
         if (rc == SSPCG_OK) rc = launch_x_pending<T>(n, s, Q, alpha, ld, x, ctrl, st);
         return rc;
     }
-    rc = run_polled(ctrl, hctrl, max_iter, p->check_every, st, step, on_batch);
+    rc = run_polled(ctrl, hctrl, max_iter, p->check_every, st, ev, step, on_batch);
     if (rc == SSPCG_OK && prof) tm.fill(prof, s, hctrl[0].iter);
     if (rc == SSPCG_OK) rc = launch_x_pending<T>(n, s, Q, alpha, ld, x, ctrl, st);
     return rc;
@@ -484,13 +512,13 @@ int setup_sums(Ctrl* hctrl, Ctrl* dctrl, const double* part, int G, double* out,
     return SSPCG_OK;
 }
 
+// GPU time of a solve between two of the solve's events.
 struct Timer {
     hipEvent_t a = nullptr, b = nullptr;
     hipStream_t st;
-    explicit Timer(hipStream_t s) : st(s)
+    Timer(const SolveEvents& ev, hipStream_t s) : a(ev.t0), b(ev.t1), st(s)
     {
-        if (hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess)
-            (void)hipEventRecord(a, st);
+        (void)hipEventRecord(a, st);
     }
     double stop()
     {
@@ -498,11 +526,6 @@ struct Timer {
         if (a && b && hipEventRecord(b, st) == hipSuccess && hipEventSynchronize(b) == hipSuccess)
             (void)hipEventElapsedTime(&ms, a, b);
         return ms;
-    }
-    ~Timer()
-    {
-        if (a) (void)hipEventDestroy(a);
-        if (b) (void)hipEventDestroy(b);
     }
 };
 
@@ -521,15 +544,15 @@ int true_relres(const sspcg_matrix* A, const double* b, const double* x, double*
 }
 
 int solve_fp64(const sspcg_matrix* A, const double* b, double* x, const sspcg_params* p,
-               const Workspace& w, char* base, Ctrl* hctrl, hipStream_t st, sspcg_result* res,
-               double* history, sspcg_profile* prof)
+               const Workspace& w, char* base, Ctrl* hctrl, const SolveEvents& ev,
+               hipStream_t st, sspcg_result* res, double* history, sspcg_profile* prof)
 {
     Ctrl* ctrl = reinterpret_cast<Ctrl*>(base + w.ctrl);
     double* part = reinterpret_cast<double*>(base + w.part);
     double* dhist = reinterpret_cast<double*>(base + w.hist);
     double* r = reinterpret_cast<double*>(base + w.vec);
     double* Z = r + w.ld;
-    Timer tm(st);
+    Timer tm(ev, st);
     int G = 0;
     int rc = launch_residual<double>(A, x, b, r, Z, part, &G, st);
     double sums[4];
@@ -558,7 +581,7 @@ int solve_fp64(const sspcg_matrix* A, const double* b, double* x, const sspcg_pa
     rc = init_ctrl(hctrl, ctrl, nb, p->tol, p->max_outer, 0.0, st);
     if (rc == SSPCG_OK)
         rc = run_sspcg<double>(A, p, w, base, x, A->dinv, p->max_outer, history ? dhist : nullptr,
-                               hctrl, prof, st);
+                               hctrl, prof, ev, st);
     res->device_ms = tm.stop();
     if (rc != SSPCG_OK) return res->status = rc;
     const Ctrl c = hctrl[0];
@@ -574,15 +597,15 @@ int solve_fp64(const sspcg_matrix* A, const double* b, double* x, const sspcg_pa
 }
 
 int solve_mixed(const sspcg_matrix* A, const double* b, double* x, const sspcg_params* p,
-                const Workspace& w, char* base, Ctrl* hctrl, hipStream_t st, sspcg_result* res,
-                double* history, sspcg_profile* prof)
+                const Workspace& w, char* base, Ctrl* hctrl, const SolveEvents& ev,
+                hipStream_t st, sspcg_result* res, double* history, sspcg_profile* prof)
 {
     Ctrl* ctrl = reinterpret_cast<Ctrl*>(base + w.ctrl);
     double* part = reinterpret_cast<double*>(base + w.part);
     float* r = reinterpret_cast<float*>(base + w.vec);
     float* Z = r + w.ld;
     float* d = r + (int64_t)(4 * p->s + 1) * w.ld;
-    Timer tm(st);
+    Timer tm(ev, st);
     double nb = 0.0, relres = 0.0;
     int nref = 0, inner_total = 0, status = SSPCG_NOT_CONVERGED;
     for (;;) {
@@ -627,7 +650,7 @@ int solve_mixed(const sspcg_matrix* A, const double* b, double* x, const sspcg_p
         if (rc == SSPCG_OK) rc = launch_fill<float>(A->n, d, 0.0f, st);
         if (rc == SSPCG_OK)
             rc = run_sspcg<float>(A, p, w, base, d, A->dinv32, p->max_outer, nullptr, hctrl, prof,
-                                  st);
+                                  ev, st);
         if (rc != SSPCG_OK) return rc;
         const Ctrl c = hctrl[0];
         inner_total += c.iter;
@@ -649,8 +672,8 @@ int solve_mixed(const sspcg_matrix* A, const double* b, double* x, const sspcg_p
 }
 
 int solve_pcg(const sspcg_matrix* A, const double* b, double* x, const sspcg_params* p,
-              const Workspace& w, char* base, Ctrl* hctrl, hipStream_t st, sspcg_result* res,
-              double* history)
+              const Workspace& w, char* base, Ctrl* hctrl, const SolveEvents& ev, hipStream_t st,
+              sspcg_result* res, double* history)
 {
     Ctrl* ctrl = reinterpret_cast<Ctrl*>(base + w.ctrl);
     double* part = reinterpret_cast<double*>(base + w.part);
@@ -661,7 +684,7 @@ int solve_pcg(const sspcg_matrix* A, const double* b, double* x, const sspcg_par
     double* pv = z + w.ld;
     double* q = pv + w.ld;
     const int64_t n = A->n;
-    Timer tm(st);
+    Timer tm(ev, st);
     int G = 0;
     double sums[4];
     int rc = launch_residual<double>(A, x, b, r, z, part2, &G, st);
@@ -698,7 +721,7 @@ int solve_pcg(const sspcg_matrix* A, const double* b, double* x, const sspcg_par
         if (e == SSPCG_OK) e = launch_pcg_pupdate(n, k, z, pv, part2, g2, ctrl, hist, st);
         return e;
     };
-    rc = run_polled(ctrl, hctrl, p->max_outer, p->check_every, st, step);
+    rc = run_polled(ctrl, hctrl, p->max_outer, p->check_every, st, ev, step);
     res->device_ms = tm.stop();
     if (rc != SSPCG_OK) return res->status = rc;
     const Ctrl c = hctrl[0];
@@ -827,6 +850,41 @@ int check_poll(void* poll)
         return arg_error("poll is not pinned host memory (hipHostMalloc or pin_memory)");
     }
     if (at.type != hipMemoryTypeHost) return arg_error("poll must be pinned host memory");
+    return SSPCG_OK;
+}
+
+// Per-device state of sspcg_solve_static, made at the first call on a
+// device with that device current: the device address of `scratch` there
+// and the solve's HIP events.  Both are kept until the process ends.
+struct StaticState {
+    void* scratch = nullptr;
+    SolveEvents ev;
+};
+constexpr int kMaxDevices = 64;
+std::mutex g_static_mu;
+StaticState g_static[kMaxDevices];
+bool g_static_ready[kMaxDevices] = {};
+
+int static_state(int dev, const StaticState** out)
+{
+    if (dev < 0 || dev >= kMaxDevices) return arg_error("device index out of range");
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    StaticState& S = g_static[dev];
+    if (!g_static_ready[dev]) {
+        void* ptr = nullptr;
+        SSPCG_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) {
+            set_error("hipGetSymbolAddress returned no address for the static scratch");
+            return SSPCG_ERR_HIP;
+        }
+        OwnedEvents ev;
+        RETURN_IF(ev.create());
+        S.scratch = ptr;
+        S.ev = ev.ev;
+        ev.ev = SolveEvents();   // kept: the state owns them now
+        g_static_ready[dev] = true;
+    }
+    *out = &S;
     return SSPCG_OK;
 }
 
@@ -1064,9 +1122,48 @@ int sspcg_solve(const sspcg_matrix* A, const double* b, double* x, const sspcg_p
     Ctrl* hctrl = static_cast<Ctrl*>(poll);
     sspcg_profile* prof = p->profile ? profile : nullptr;
     if (prof) std::memset(prof, 0, sizeof(*prof));
+    OwnedEvents ev;
+    RETURN_IF(ev.create());
     if (p->precision == SSPCG_MIXED)
-        return solve_mixed(A, b, x, p, w, base, hctrl, st, res, history, prof);
-    return solve_fp64(A, b, x, p, w, base, hctrl, st, res, history, prof);
+        return solve_mixed(A, b, x, p, w, base, hctrl, ev.ev, st, res, history, prof);
+    return solve_fp64(A, b, x, p, w, base, hctrl, ev.ev, st, res, history, prof);
+    API_CATCH
+}
+
+int sspcg_solve_static(const sspcg_matrix* A, const double* b, double* x, const sspcg_params* p,
+                       void* poll, sspcg_stream stream, sspcg_result* res)
+{
+    API_TRY
+    RETURN_IF(check_matrix(A));
+    if (!res) return arg_error("res is NULL");
+    std::memset(res, 0, sizeof(*res));
+    RETURN_IF(check_vec(b, SSPCG_F64, "b"));
+    RETURN_IF(check_vec(x, SSPCG_F64, "x"));
+    RETURN_IF(check_params(A, p, false));
+    RETURN_IF(check_poll(poll));
+    if (p->profile || p->use_graph) {
+        set_error("sspcg_solve_static: profile and use_graph need HIP events or graphs it does "
+                  "not create; use sspcg_solve");
+        return res->status = SSPCG_ERR_UNSUPPORTED;
+    }
+    const Workspace w = layout_sspcg(A->n, p);
+    if (w.total > (size_t)SSPCG_STATIC_SCRATCH_BYTES) {
+        set_error("sspcg_solve_static: the solve needs " + std::to_string(w.total) +
+                  " bytes of workspace, more than the static scratch of " +
+                  std::to_string((size_t)SSPCG_STATIC_SCRATCH_BYTES) + " bytes; use sspcg_solve");
+        return res->status = SSPCG_ERR_WORKSPACE;
+    }
+    int dev = -1;
+    SSPCG_HIP(hipGetDevice(&dev));
+    if (dev != A->device) return arg_error("the current device is not the matrix's device");
+    const StaticState* sst = nullptr;
+    RETURN_IF(static_state(dev, &sst));
+    hipStream_t st = as_stream(stream);
+    char* base = static_cast<char*>(sst->scratch);
+    Ctrl* hctrl = static_cast<Ctrl*>(poll);
+    if (p->precision == SSPCG_MIXED)
+        return solve_mixed(A, b, x, p, w, base, hctrl, sst->ev, st, res, nullptr, nullptr);
+    return solve_fp64(A, b, x, p, w, base, hctrl, sst->ev, st, res, nullptr, nullptr);
     API_CATCH
 }
 
@@ -1088,7 +1185,9 @@ int sspcg_pcg_solve(const sspcg_matrix* A, const double* b, double* x, const ssp
         set_error("workspace too small");
         return res->status = SSPCG_ERR_WORKSPACE;
     }
-    return solve_pcg(A, b, x, p, w, static_cast<char*>(work), static_cast<Ctrl*>(poll),
+    OwnedEvents ev;
+    RETURN_IF(ev.create());
+    return solve_pcg(A, b, x, p, w, static_cast<char*>(work), static_cast<Ctrl*>(poll), ev.ev,
                      as_stream(stream), res, history);
     API_CATCH
 }
