@@ -180,7 +180,8 @@ def main() -> int:
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-profile", action="store_true",
                     help="time without the per-phase HIP events")
-    ap.add_argument("--mode", choices=["solve", "kernels", "paper", "configs", "seeds"],
+    ap.add_argument("--mode", choices=["solve", "kernels", "paper", "configs", "seeds",
+                                       "traffic-record", "trace-summary"],
                     default="solve",
                     help="kernels: a few launches of each hot kernel on the workload and a "
                          "copy kernel of known size (for rocprofv3 counter passes); paper: the "
@@ -190,7 +191,22 @@ def main() -> int:
     ap.add_argument("--paper-out", default=None,
                     help="paper mode: also write the per-iteration histories to this JSON file")
     ap.add_argument("--reps", type=int, default=5)
+    ap.add_argument("--trace-dir", default="gpurun_out/prof_bench",
+                    help="trace-summary: output directory of a rocprofv3 --kernel-trace run")
+    ap.add_argument("--fetch-dir", default="gpurun_out/pmc_FETCH_SIZE",
+                    help="traffic-record: output directory of the rocprofv3 --pmc FETCH_SIZE pass")
+    ap.add_argument("--write-dir", default="gpurun_out/pmc_WRITE_SIZE",
+                    help="traffic-record: output directory of the rocprofv3 --pmc WRITE_SIZE pass")
     args = ap.parse_args()
+    if args.mode == "trace-summary":
+        print(trace_summary(args.trace_dir))
+        return 0
+    if args.mode == "traffic-record":
+        # host only: turns two counter passes over --mode kernels into the
+        # traffic record the roofline object reads
+        rec = traffic_record(args.fetch_dir, args.write_dir, args.s)
+        print(json.dumps(rec, indent=1))
+        return 0
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -487,6 +503,121 @@ def accuracy_vs_oracle(P, M, b, A, b_np, interval, args, with_mixed=True) -> dic
     return out
 
 
+TRAFFIC_SOURCES = ["paper_2603_09790_amd/csrc/sell.hip", "paper_2603_09790_amd/csrc/common.h"]
+
+
+def counter_dispatches(outdir: str, counter: str) -> list:
+    """(kernel short name, value) of `counter` for every dispatch in the
+    rocprofv3 database(s) (*_results.db, SQLite) under outdir."""
+    import glob
+    import sqlite3
+    files = glob.glob(os.path.join(outdir, "**", "*_results.db"), recursive=True)
+    if not files:
+        raise FileNotFoundError(f"no rocprofv3 *_results.db under {outdir}")
+    out = []
+    for f in files:
+        con = sqlite3.connect(f)
+        q = ("select dispatch_id, kernel_name, sum(value) from counters_collection "
+             "where counter_name = ? group by dispatch_id, kernel_name")
+        out += [(short_kernel_name(name), float(v)) for _, name, v in con.execute(q, (counter,))]
+        con.close()
+    return out
+
+
+def trace_summary(outdir: str, min_pct: float = 0.01) -> str:
+    """Markdown table of a rocprofv3 kernel trace (*_results.db under
+    outdir): calls, total, average, min and max duration per kernel."""
+    import glob
+    import sqlite3
+    files = glob.glob(os.path.join(outdir, "**", "*_results.db"), recursive=True)
+    if not files:
+        raise FileNotFoundError(f"no rocprofv3 *_results.db under {outdir}")
+    per = {}
+    for f in files:
+        con = sqlite3.connect(f)
+        for name, dur in con.execute("select name, duration from kernels"):
+            per.setdefault(short_kernel_name(name), []).append(float(dur))
+        con.close()
+    total = sum(sum(v) for v in per.values())
+    lines = ["| kernel | calls | total ms | avg us | min us | max us | % |",
+             "|---|---:|---:|---:|---:|---:|---:|"]
+    for k, v in sorted(per.items(), key=lambda kv: -sum(kv[1])):
+        pct = 100.0 * sum(v) / total
+        if pct < min_pct:
+            continue
+        lines.append(f"| `{k}` | {len(v)} | {sum(v) / 1e6:.2f} | {np.mean(v) / 1e3:.1f} | "
+                     f"{min(v) / 1e3:.1f} | {max(v) / 1e3:.1f} | {pct:.2f} |")
+    return "\n".join(lines)
+
+
+def counter_rows(outdir: str, counter: str) -> dict:
+    """Per kernel, the mean value of `counter` per dispatch; for the device
+    copy (several sizes in one run) the largest dispatch, the 1 GiB copy."""
+    vals = {}
+    for name, v in counter_dispatches(outdir, counter):
+        vals.setdefault(name, []).append(v)
+    return {k: float(max(v) if "copyBuffer" in k else np.mean(v)) for k, v in vals.items()}
+
+
+def short_kernel_name(full: str) -> str:
+    """'void sspcg::(anonymous namespace)::k_spmv<double, 0>(...)' -> 'k_spmv<double, 0>'."""
+    import re
+    m = re.search(r"\b(k_\w+(?:<[^()]*?>)?)\s*\(", full) or re.search(r"\b(k_\w+(?:<[^()]*?>)?)", full)
+    if m:
+        return m.group(1)
+    return "__amd_rocclr_copyBuffer" if "copyBuffer" in full else full
+
+
+def traffic_record(fetch_dir: str, write_dir: str, s: int) -> dict:
+    """HBM-side bytes per SpMV launch of the matrix powers kernel from the
+    FETCH_SIZE and WRITE_SIZE passes (KiB per dispatch) over --mode kernels,
+    each scaled by what the same counter reads for the 1 GiB device copy of
+    that run; written to profiles/ with a hash of the SpMV sources."""
+    import hashlib
+    fetch = counter_rows(fetch_dir, "FETCH_SIZE")
+    write = counter_rows(write_dir, "WRITE_SIZE")
+    ck = "__amd_rocclr_copyBuffer"     # largest dispatch: the 1 GiB calibration copy
+    if ck not in fetch or ck not in write:
+        raise RuntimeError("the counter passes hold no device copy to calibrate with")
+    fscale = COPY_BYTES / (fetch[ck] * 1024.0)
+    wscale = COPY_BYTES / (write[ck] * 1024.0)
+    modes = {}
+    for k in fetch:
+        if k.startswith("k_spmv<double"):
+            mode = k.split(",")[1].strip().rstrip(">").strip()
+            name = f"k_spmv<double, {mode}>"
+            modes[name] = {"fetch_kib": fetch[k], "write_kib": write.get(k, 0.0),
+                           "traffic_bytes": fetch[k] * 1024.0 * fscale
+                           + write.get(k, 0.0) * 1024.0 * wscale}
+    need = ["k_spmv<double, 0>", "k_spmv<double, 1>", "k_spmv<double, 2>"]
+    if any(m not in modes for m in need):
+        raise RuntimeError(f"counter passes lack SpMV modes: found {sorted(modes)}")
+    per_launch = (modes[need[1]]["traffic_bytes"] + (s - 2) * modes[need[2]]["traffic_bytes"]
+                  + modes[need[0]]["traffic_bytes"]) / s
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    rec = {"kernel": "k_spmv (matrix powers kernel, FP64)",
+           "workload": f"27-point diffusion 192^3, s = {s}",
+           "source_sha256": h.hexdigest(), "sources": TRAFFIC_SOURCES,
+           "calibration": {"kernel": ck + " (1 GiB device copy)", "bytes_each_way": COPY_BYTES,
+                           "fetch_kib": fetch[ck], "write_kib": write[ck],
+                           "fetch_scale": fscale, "write_scale": wscale},
+           "modes": modes, "traffic_bytes_per_launch": per_launch,
+           "note": "average over the s launches of one matrix powers kernel: modes 1, "
+                   "(s-2) x 2 and 0",
+           "commands": [
+               "export TMPDIR=/tmp; timeout -s KILL 180 rocprofv3 --pmc FETCH_SIZE -d "
+               "gpurun_out/pmc_FETCH_SIZE -o kern -- python3 bench.py --mode kernels --reps 2",
+               "export TMPDIR=/tmp; timeout -s KILL 180 rocprofv3 --pmc WRITE_SIZE -d "
+               "gpurun_out/pmc_WRITE_SIZE -o kern -- python3 bench.py --mode kernels --reps 2",
+               "python3 bench.py --mode traffic-record"]}
+    with open(TRAFFIC_RECORD, "w") as f:
+        json.dump(rec, f, indent=1)
+        f.write("\n")
+    return rec
+
+
 def seed_spread(P, torch, dev, args, nseeds=5):
     """FP64 and mixed solves of the 192^3 system for nseeds right-hand sides
     b ~ N(0,1) (the benchmark's seed and the next ones): iteration counts and
@@ -656,12 +787,14 @@ def paper_experiments(P, torch, dev, args):
             aligned = hp[np.minimum(k * s, len(hp)) - 1]
             name = f"s{s}_{gram}{sweeps if gram == 'fgs' else ''}"
             runs[name] = {"relres": h[:, 0].tolist(), "eta_alpha": h[:, 1].tolist(),
-                          "eta_beta": h[:, 2].tolist(), "pcg_every_s": aligned.tolist()}
+                          "eta_beta": h[:, 2].tolist(), "conjugacy_defect": h[:, 3].tolist(),
+                          "pcg_every_s": aligned.tolist()}
             eb = h[:-1, 2] if len(h) > 1 else h[:, 2]
             summary[name] = {"outer_iters": info["outer_iters"], "krylov_steps": s * info["outer_iters"],
                              "time_s": info["device_ms"] / 1e3, "status": info["status_name"],
                              "eta_alpha_max": float(h[:, 1].max()), "eta_alpha_median": float(np.median(h[:, 1])),
                              "eta_beta_max": float(eb.max()), "eta_beta_median": float(np.median(eb)),
+                             "conjugacy_defect_median": float(np.median(h[:-1, 3] if len(h) > 1 else h[:, 3])),
                              "max_log10_gap_to_pcg": float(np.max(np.abs(np.log10(h[:, 0]) - np.log10(aligned))))}
             log(f"[paper] {name}: {summary[name]}")
     return {"summary": summary, "runs": runs, "pcg_history": hp.tolist()}

@@ -109,3 +109,48 @@ def test_oracle_record_rejects_other_inputs():
     assert rec is not None and rec["n"] == A.n
     assert bench.oracle_record("poisson5_64_s4_nu2", A, b + 1.0) is None
     assert bench.oracle_record("no_such_case", A, b) is None
+
+
+def _fake_rocpd(path, kernels, counters):
+    import sqlite3
+    con = sqlite3.connect(path)
+    con.execute("create table kernels (name text, duration integer)")
+    con.execute("create table counters_collection (dispatch_id integer, kernel_name text, "
+                "counter_name text, value real)")
+    con.executemany("insert into kernels values (?, ?)", kernels)
+    con.executemany("insert into counters_collection values (?, ?, ?, ?)", counters)
+    con.commit()
+    con.close()
+
+
+def test_counter_passes_make_the_traffic_record(tmp_path, monkeypatch):
+    spmv = "void sspcg::(anonymous namespace)::k_spmv<double, {}>(sspcg::Sell<double>, double const*)"
+    f, w = tmp_path / "f", tmp_path / "w"
+    f.mkdir()
+    w.mkdir()
+    # the 1 GiB copy (FETCH_SIZE counts half its reads) and a smaller copy
+    fetch = [(1, "__amd_rocclr_copyBuffer", "FETCH_SIZE", 524288.0),
+             (2, "__amd_rocclr_copyBuffer", "FETCH_SIZE", 1.0)]
+    write = [(1, "__amd_rocclr_copyBuffer", "WRITE_SIZE", 1048576.0),
+             (2, "__amd_rocclr_copyBuffer", "WRITE_SIZE", 2.0)]
+    for m, kib in ((0, 1000.0), (1, 2000.0), (2, 3000.0)):
+        fetch += [(10 + m, spmv.format(m), "FETCH_SIZE", kib), (20 + m, spmv.format(m), "FETCH_SIZE", kib)]
+        write += [(10 + m, spmv.format(m), "WRITE_SIZE", 100.0), (20 + m, spmv.format(m), "WRITE_SIZE", 100.0)]
+    _fake_rocpd(f / "kern_results.db", [], fetch)
+    _fake_rocpd(w / "kern_results.db", [], write)
+    monkeypatch.setattr(bench, "TRAFFIC_RECORD", str(tmp_path / "rec.json"))
+    rec = bench.traffic_record(str(f), str(w), 6)
+    assert rec["calibration"]["fetch_scale"] == 2.0 and rec["calibration"]["write_scale"] == 1.0
+    per = {m: (2 * kib + 100.0) * 1024 for m, kib in ((0, 1000.0), (1, 2000.0), (2, 3000.0))}
+    assert rec["modes"]["k_spmv<double, 1>"]["traffic_bytes"] == per[1]
+    assert abs(rec["traffic_bytes_per_launch"] - (per[1] + 4 * per[2] + per[0]) / 6) < 1e-6
+    # the record guards itself against source changes
+    assert bench.counter_traffic() == rec["traffic_bytes_per_launch"]
+
+
+def test_trace_summary_table(tmp_path):
+    k0 = "void sspcg::(anonymous namespace)::k_spmv<double, 0>(sspcg::Sell<double>)"
+    _fake_rocpd(tmp_path / "b_results.db", [(k0, 200000), (k0, 220000), ("k_norm_step(x)", 5000)], [])
+    t = bench.trace_summary(str(tmp_path))
+    assert "| `k_spmv<double, 0>` | 2 | 0.42 | 210.0 | 200.0 | 220.0 |" in t
+    assert "`k_norm_step`" in t

@@ -4,8 +4,10 @@
    tests/golden/make_solution_records.py from the CPU oracle alone): the
    2D Poisson 64^2 system, the 7-point Poisson 128^3 (s, nu) grid and the
    27-point heterogeneous 192^3 benchmark system.  Both sides run
-   Algorithm 1 with the same interval, s and nu to a relative residual of
-   1e-12; the device solution must agree with the oracle's to 1e-10 in the
+   Algorithm 1 with the same interval, s and nu to the record's relative
+   residual (1e-14; classical PCG 1e-13): two correct solves to tau differ by
+   up to kappa_2(A) tau, so 1e-12 would not support the 1e-10 bar on the
+   128^3 system.  The device solution must agree with the oracle's to 1e-10 in the
    sampled entries, the norm and the projections on seeded random vectors,
    and in the 2-norm error estimated from the uniformly sampled entries.
 2. At the benchmark tolerance 1e-8, where the two iterations may part by
@@ -21,12 +23,12 @@ import os
 
 import numpy as np
 import pytest
-import scipy.sparse.linalg as spl
 import torch
 
 import oracle
 import paper_2603_09790_amd as P
 import sspcg_inputs as si
+from spectral import kappa2
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
@@ -83,14 +85,6 @@ def test_solution_matches_oracle_record(path):
     # both iterations stop at the same tolerance; the counts may differ by
     # rounding (two FGS sweeps solve the Gram systems only roughly)
     assert abs(info["outer_iters"] - rec["iters"]) <= 0.25 * rec["iters"] + 2
-
-
-def kappa2(A) -> float:
-    """kappa_2(A) = lambda_max / lambda_min of the SPD matrix (ARPACK)."""
-    S = si.to_scipy(A).tocsc()
-    hi = spl.eigsh(S, k=1, which="LA", return_eigenvectors=False, tol=1e-8)[0]
-    lo = spl.eigsh(S, k=1, sigma=0.0, which="LM", return_eigenvectors=False, tol=1e-8)[0]
-    return float(hi / lo)
 
 
 @pytest.mark.parametrize("name,N", [("poisson5", 64), ("diffusion27", 24)])
