@@ -34,6 +34,10 @@
 #include <omp.h>
 #endif
 
+/* Loops over fewer rows than this run on one thread (threads cost more
+ * than they save there, and compete with other work on the host). */
+#define OR_PAR_MIN 32768
+
 enum {
     OR_OK = 0, OR_NOT_CONVERGED = 1, OR_ERR_ARG = -1, OR_BREAKDOWN = -3,
     OR_NONFINITE = -5
@@ -83,7 +87,7 @@ double or_nrm2(int64_t n, const double* a) { return sqrt(or_dot(n, a, a)); }
 void or_spmv(int64_t n, const int32_t* rp, const int32_t* col, const double* val,
              const double* x, double* y)
 {
-    #pragma omp parallel for schedule(static)
+    #pragma omp parallel for schedule(static) if (n >= OR_PAR_MIN)
     for (int64_t i = 0; i < n; ++i) {
         double acc = 0.0;
         for (int32_t e = rp[i]; e < rp[i + 1]; ++e) acc += val[e] * x[col[e]];
@@ -97,7 +101,7 @@ void or_spmv(int64_t n, const int32_t* rp, const int32_t* col, const double* val
 void or_spmv_f32(int64_t n, const int32_t* rp, const int32_t* col, const float* val,
                  const float* x, float* y)
 {
-    #pragma omp parallel for schedule(static)
+    #pragma omp parallel for schedule(static) if (n >= OR_PAR_MIN)
     for (int64_t i = 0; i < n; ++i) {
         double acc = 0.0;
         for (int32_t e = rp[i]; e < rp[i + 1]; ++e)
@@ -164,7 +168,7 @@ void or_mpk_basis(int64_t n, const int32_t* rp, const int32_t* col, const double
     #define ZP(q) (zp + (int64_t)((q) - 1) * n)
     #define ZC(q) (Z + (int64_t)((q) - 1) * ld)
     #define PC(q) (P + (int64_t)((q) - 1) * ld)
-    #pragma omp parallel for schedule(static)
+    #pragma omp parallel for schedule(static) if (n >= OR_PAR_MIN)
     for (int64_t i = 0; i < n; ++i) {
         PC(1)[i] = r[i];
         ZP(1)[i] = PC(1)[i];
@@ -173,7 +177,7 @@ void or_mpk_basis(int64_t n, const int32_t* rp, const int32_t* col, const double
     if (basis == 1) {
         for (int q = 1; q <= s - 1; ++q) {
             or_spmv(n, rp, col, val, ZC(q), PC(q + 1));
-            #pragma omp parallel for schedule(static)
+            #pragma omp parallel for schedule(static) if (n >= OR_PAR_MIN)
             for (int64_t i = 0; i < n; ++i) {
                 ZP(q + 1)[i] = PC(q + 1)[i];
                 ZC(q + 1)[i] = dinv[i] * ZP(q + 1)[i];
@@ -181,14 +185,14 @@ void or_mpk_basis(int64_t n, const int32_t* rp, const int32_t* col, const double
         }
     } else if (s > 1) {
         or_spmv(n, rp, col, val, ZC(1), PC(2));
-        #pragma omp parallel for schedule(static)
+        #pragma omp parallel for schedule(static) if (n >= OR_PAR_MIN)
         for (int64_t i = 0; i < n; ++i) {
             ZP(2)[i] = al * PC(2)[i] - sg * ZP(1)[i];
             ZC(2)[i] = dinv[i] * ZP(2)[i];
         }
         for (int q = 2; q <= s - 1; ++q) {
             or_spmv(n, rp, col, val, ZC(q), PC(q + 1));
-            #pragma omp parallel for schedule(static)
+            #pragma omp parallel for schedule(static) if (n >= OR_PAR_MIN)
             for (int64_t i = 0; i < n; ++i) {
                 ZP(q + 1)[i] = 2.0 * al * PC(q + 1)[i] - 2.0 * sg * ZP(q)[i] - gm * ZP(q - 1)[i];
                 ZC(q + 1)[i] = dinv[i] * ZP(q + 1)[i];
@@ -212,7 +216,7 @@ void or_gram(int64_t n, int s, const double* Q, const double* AQ, const double* 
 {
     /* task t < s(s+1)/2: entry (i, j), i >= j, in row order; then b1_i */
     const int nw = s * (s + 1) / 2;
-    #pragma omp parallel for schedule(dynamic, 1)
+    #pragma omp parallel for schedule(dynamic, 1) if (n >= OR_PAR_MIN)
     for (int t = 0; t < nw + s; ++t) {
         if (t >= nw) {
             const int i = t - nw;
@@ -232,7 +236,7 @@ void or_gram(int64_t n, int s, const double* Q, const double* AQ, const double* 
 void or_gram_rect(int64_t n, int s, const double* Q, const double* AZ, int64_t ld,
                   double* B2)
 {
-    #pragma omp parallel for schedule(dynamic, 1)
+    #pragma omp parallel for schedule(dynamic, 1) if (n >= OR_PAR_MIN)
     for (int t = 0; t < s * s; ++t) {
         const int i = t / s, j = t % s;
         B2[i * s + j] = -or_dot(n, Q + (int64_t)i * ld, AZ + (int64_t)j * ld);
@@ -344,7 +348,7 @@ int or_chol_solve(int s, int nrhs, const double* W, const double* B, double* X)
 void or_xr_update(int64_t n, int s, const double* Q, const double* AQ,
                   const double* alpha, int64_t ld, double* x, double* r)
 {
-    #pragma omp parallel for schedule(static)
+    #pragma omp parallel for schedule(static) if (n >= OR_PAR_MIN)
     for (int64_t i = 0; i < n; ++i) {
         double qa = 0.0, aqa = 0.0;
         for (int j = 0; j < s; ++j) {
@@ -360,7 +364,7 @@ void or_xr_update(int64_t n, int s, const double* Q, const double* AQ,
 void or_block_update(int64_t n, int s, const double* Z, double* Q, const double* AZ,
                      double* AQ, const double* beta, int64_t ld)
 {
-    #pragma omp parallel for schedule(static)
+    #pragma omp parallel for schedule(static) if (n >= OR_PAR_MIN)
     for (int64_t i = 0; i < n; ++i) {
         double q[64], aq[64];
         for (int j = 0; j < s; ++j) {
@@ -656,7 +660,7 @@ void or_mpk_f32(int64_t n, const int32_t* rp, const int32_t* col, const float* v
     #define ZP(q) (zp + (int64_t)((q) - 1) * n)
     #define ZC(q) (Z + (int64_t)((q) - 1) * ld)
     #define PC(q) (P + (int64_t)((q) - 1) * ld)
-    #pragma omp parallel for schedule(static)
+    #pragma omp parallel for schedule(static) if (n >= OR_PAR_MIN)
     for (int64_t i = 0; i < n; ++i) {
         PC(1)[i] = r[i];
         ZP(1)[i] = PC(1)[i];
@@ -664,14 +668,14 @@ void or_mpk_f32(int64_t n, const int32_t* rp, const int32_t* col, const float* v
     }
     if (s > 1) {
         or_spmv_f32(n, rp, col, val, ZC(1), PC(2));
-        #pragma omp parallel for schedule(static)
+        #pragma omp parallel for schedule(static) if (n >= OR_PAR_MIN)
         for (int64_t i = 0; i < n; ++i) {
             ZP(2)[i] = (float)(al * (double)PC(2)[i] - sg * (double)ZP(1)[i]);
             ZC(2)[i] = (float)((double)dinv[i] * (double)ZP(2)[i]);
         }
         for (int q = 2; q <= s - 1; ++q) {
             or_spmv_f32(n, rp, col, val, ZC(q), PC(q + 1));
-            #pragma omp parallel for schedule(static)
+            #pragma omp parallel for schedule(static) if (n >= OR_PAR_MIN)
             for (int64_t i = 0; i < n; ++i) {
                 ZP(q + 1)[i] = (float)(2.0 * al * (double)PC(q + 1)[i] - 2.0 * sg * (double)ZP(q)[i]
                                        - gm * (double)ZP(q - 1)[i]);
@@ -691,7 +695,7 @@ void or_gram_f32(int64_t n, int s, const float* Q, const float* AQ, const float*
 {
     /* the tasks of or_gram */
     const int nw = s * (s + 1) / 2;
-    #pragma omp parallel for schedule(dynamic, 1)
+    #pragma omp parallel for schedule(dynamic, 1) if (n >= OR_PAR_MIN)
     for (int t = 0; t < nw + s; ++t) {
         if (t >= nw) {
             const int i = t - nw;
@@ -710,7 +714,7 @@ void or_gram_f32(int64_t n, int s, const float* Q, const float* AQ, const float*
 void or_gram_rect_f32(int64_t n, int s, const float* Q, const float* AZ, int64_t ld,
                       double* B2)
 {
-    #pragma omp parallel for schedule(dynamic, 1)
+    #pragma omp parallel for schedule(dynamic, 1) if (n >= OR_PAR_MIN)
     for (int t = 0; t < s * s; ++t) {
         const int i = t / s, j = t % s;
         B2[i * s + j] = -dot_f32(n, Q + (int64_t)i * ld, AZ + (int64_t)j * ld);
@@ -720,7 +724,7 @@ void or_gram_rect_f32(int64_t n, int s, const float* Q, const float* AZ, int64_t
 void or_xr_update_f32(int64_t n, int s, const float* Q, const float* AQ,
                       const double* alpha, int64_t ld, float* x, float* r)
 {
-    #pragma omp parallel for schedule(static)
+    #pragma omp parallel for schedule(static) if (n >= OR_PAR_MIN)
     for (int64_t i = 0; i < n; ++i) {
         double qa = 0.0, aqa = 0.0;
         for (int j = 0; j < s; ++j) {
@@ -735,7 +739,7 @@ void or_xr_update_f32(int64_t n, int s, const float* Q, const float* AQ,
 void or_block_update_f32(int64_t n, int s, const float* Z, float* Q, const float* AZ,
                          float* AQ, const double* beta, int64_t ld)
 {
-    #pragma omp parallel for schedule(static)
+    #pragma omp parallel for schedule(static) if (n >= OR_PAR_MIN)
     for (int64_t i = 0; i < n; ++i) {
         double q[64], aq[64];
         for (int j = 0; j < s; ++j) {

@@ -74,12 +74,12 @@ __global__ __launch_bounds__(kRowBlock) void k_update_gram(int64_t n, int64_t ld
     for (int64_t t = tr.first; t < tr.end; t += tr.step) {
         const int64_t i = t * kRowBlock + threadIdx.x;
         if (i >= n) break;
-        // FP32: every load of the row is issued before its first store (the
-        // wait counter is shared by loads and stores, so a load queued behind
-        // a store also waits for the store; 271 -> 217 us per FP32 update at
-        // 192^3).  FP64 loads Z and AZ column by column between the stores:
-        // holding all its operands at once costs a wave per SIMD.
-        constexpr bool kPreload = sizeof(T) == 4;
+        // Every load of the row is issued before its first store (the wait
+        // counter is shared by loads and stores, so a load queued behind a
+        // store also waits for the store): 271 -> 217 us per FP32 update at
+        // 192^3, 420 -> 407 us per FP64 update (all operands held at once
+        // cost a wave per SIMD, but the loads are in flight together).
+        constexpr bool kPreload = true;
         double q[S], aq[S];
         T zv[S], azv[S];
         T rv = (T)0;
@@ -357,10 +357,10 @@ int row_grid(int64_t n)
 // Persistent grid of a block kernel: up to 8 workgroups per CU, no more than
 // fit at once.
 template <typename K>
-static int block_grid(int64_t n, K kernel)
+static int block_grid(int64_t n, K kernel, int blocks_per_cu = 8)
 {
     const int resident = resident_blocks(reinterpret_cast<const void*>(kernel), kRowBlock);
-    return persistent_grid((n + kRowBlock - 1) / kRowBlock, 8, resident);
+    return persistent_grid((n + kRowBlock - 1) / kRowBlock, blocks_per_cu, resident);
 }
 
 #define SSPCG_S_CASES(X) \
@@ -404,9 +404,13 @@ template <typename T>
 int launch_gram_rect(int64_t n, int s, const T* Q, const T* AZ, int64_t ld, double* partials,
                      int* G_out, const Ctrl* ctrl, hipStream_t st)
 {
-    // FP32 columns whose elements 4i.. are 16-byte aligned go 4 rows per
-    // thread; anything else one row per thread
-    constexpr int RV = sizeof(T) == 4 ? 4 : 1;
+    // columns whose elements R i.. are 16-byte aligned go R rows per thread
+    // as one 16-byte vector per column (4 FP32 or 2 FP64 rows); anything
+    // else one row per thread.  FP64 at 192^3: 133 us with one row per thread
+    // at 8-byte loads, 110 us with two rows and two workgroups per CU (the
+    // read-only stream then runs at 6.1 TB/s)
+    constexpr int RV = sizeof(T) == 4 ? 4 : 2;
+    constexpr int kBlocksPerCu = sizeof(T) == 4 ? 8 : 2;
     const bool vec = RV > 1 && ld % RV == 0 && reinterpret_cast<uintptr_t>(Q) % 16 == 0 &&
                      reinterpret_cast<uintptr_t>(AZ) % 16 == 0;
     const int64_t units = vec ? (n + RV - 1) / RV : n;
@@ -415,7 +419,7 @@ int launch_gram_rect(int64_t n, int s, const T* Q, const T* AZ, int64_t ld, doub
 #define X(S)                                                                                   \
     case S:                                                                                    \
         if (vec) {                                                                             \
-            G = block_grid(units, k_gram_rect<S, T, RV>);                                      \
+            G = block_grid(units, k_gram_rect<S, T, RV>, kBlocksPerCu);                        \
             hipLaunchKernelGGL((k_gram_rect<S, T, RV>), dim3(G), dim3(kRowBlock), 0, st, n, ld, \
                                Q, AZ, partials, ctrl);                                         \
         } else {                                                                               \

@@ -14,8 +14,10 @@
    rounding: both solutions lie within the forward-error bound
    kappa_2(A) ||b - A x|| / ||b|| of x_ref (oracle PCG to 1e-13), and the
    device's outer-iteration count lies within the spread of the oracle's runs
-   whose Gram entries are moved by one unit in the last place (five seeded
-   perturbations, and the unperturbed run).
+   whose Gram entries are moved by one unit in the last place (tests/spread.py:
+   within four standard deviations of 24 such runs; five runs, as first
+   planned, sample too little of a distribution that spans 291..483 on the
+   64^2 system).
 """
 import glob
 import json
@@ -29,6 +31,7 @@ import oracle
 import paper_2603_09790_amd as P
 import sspcg_inputs as si
 from spectral import kappa2
+from spread import perturbed_counts, within_spread
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
@@ -83,7 +86,9 @@ def test_solution_matches_oracle_record(path):
     assert abs(nx - rec["norm_x"]) <= SOLUTION_TOL * rec["norm_x"]
     assert pe.max() <= SOLUTION_TOL
     # both iterations stop at the same tolerance; the counts may differ by
-    # rounding (two FGS sweeps solve the Gram systems only roughly)
+    # rounding (two FGS sweeps solve the Gram systems only roughly: 60
+    # perturbed oracle runs of the 64^2 system spread over +-20 % of their
+    # mean at 1e-12, tests/spread.py)
     assert abs(info["outer_iters"] - rec["iters"]) <= 0.25 * rec["iters"] + 2
 
 
@@ -110,18 +115,18 @@ def test_tau_1e8_forward_error_and_iteration_spread(name, N):
         return err, bound
 
     eg, bg = fwd(xg)
-    counts = []
     for seed in range(6):      # 0: unperturbed; 1..5: one-ulp Gram perturbations
         xo, ro = oracle.sspcg(A, b, s=s, sweeps=nu, interval=w["interval"], tol=tol,
                               perturb_seed=seed)
         assert ro["status"] == oracle.OK
         eo, bo = fwd(xo)
         assert eo <= bo
-        counts.append(ro["iters"])
         if seed == 0:
             diff = np.linalg.norm(xg - xo) / np.linalg.norm(xo)
+    counts = perturbed_counts(A, b, s=s, sweeps=nu, interval=w["interval"], tol=tol, runs=24)
     print(f"[tau 1e-8] {name} {N}: kappa_2 {kap:.3e}; device {info['outer_iters']} outer, "
-          f"error vs x_ref {eg:.2e} (bound {bg:.2e}); oracle counts {counts}; "
+          f"error vs x_ref {eg:.2e} (bound {bg:.2e}); oracle counts {counts.min()}.."
+          f"{counts.max()} (mean {counts.mean():.1f}, sd {counts.std():.1f}); "
           f"device vs unperturbed oracle {diff:.2e}")
     assert eg <= bg
-    assert min(counts) <= info["outer_iters"] <= max(counts)
+    assert within_spread(info["outer_iters"], counts)

@@ -16,6 +16,7 @@ import oracle
 import paper_2603_09790_amd as P
 import sspcg_inputs as si
 from spectral import kappa2
+from spread import perturbed_counts, within_spread
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
@@ -76,8 +77,12 @@ def test_tight_tolerance_solution(name, request):
     assert info["status"] == P.OK and ro["status"] == oracle.OK
     assert info["relres"] <= 1e-12
     assert rel(x, xo) <= 1e-10
-    # the iteration counts of two runs that differ only in rounding
-    assert abs(info["outer_iters"] - ro["iters"]) <= max(5, 0.1 * ro["iters"])
+    # the iteration count: within the rounding-only spread of the oracle
+    counts = perturbed_counts(w["A"], w["b"], s=s, sweeps=2, interval=w["interval"], tol=1e-12,
+                              runs=16 if name == "poisson5" else 6)
+    print(f"{name}: device {info['outer_iters']} outer; perturbed oracle {counts.min()}.."
+          f"{counts.max()} (mean {counts.mean():.1f})")
+    assert within_spread(info["outer_iters"], counts)
 
 
 @pytest.mark.parametrize("s", [2, 4, 6, 8])

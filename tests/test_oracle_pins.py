@@ -597,3 +597,24 @@ def test_power_method_stop_rule():
         assert np.all(rel >= 1e-3)
     _, hi2, steps2, _ = oracle.power_bounds(A, si.start_vector(A.n), rtol=1e-3, max_iter=3)
     assert steps2 == min(3, steps) and hi2 == hist[steps2 - 1]
+
+
+# ------------------------------------------------- one-ulp Gram perturbations
+def test_gram_perturbations_are_one_ulp():
+    """perturb_seed = 0 is the plain solve; with a seed every Gram entry moves
+    by one unit in the last place: the iterates of an exact Gram solve stay
+    within rounding of the plain ones, and the iteration counts of two FGS
+    sweeps (rounding-driven) change with the seed."""
+    w = si.workload("poisson5", N=64)
+    A, b = w["A"], w["b"]
+    kw = dict(s=4, interval=w["interval"], tol=1e-10)
+    x0, r0 = oracle.sspcg(A, b, sweeps=2, **kw)
+    xs, rs = oracle.sspcg(A, b, sweeps=2, perturb_seed=0, **kw)
+    assert np.array_equal(x0, xs) and r0 == rs
+    xc, rc = oracle.sspcg(A, b, sweeps=1, gram="cholesky", **kw)
+    xp, rp = oracle.sspcg(A, b, sweeps=1, gram="cholesky", perturb_seed=7, **kw)
+    assert not np.array_equal(xc, xp)
+    assert np.linalg.norm(xp - xc) <= 1e-8 * np.linalg.norm(xc)
+    assert abs(rp["iters"] - rc["iters"]) <= 1
+    counts = {oracle.sspcg(A, b, sweeps=2, perturb_seed=k, **kw)[1]["iters"] for k in range(1, 9)}
+    assert len(counts) >= 3
