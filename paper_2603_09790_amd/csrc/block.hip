@@ -12,6 +12,8 @@
 // by the next block update, which reads that Q anyway (k_update_gram MODE 2),
 // or after the loop (k_x_pending).
 
+#include <algorithm>
+
 #include "launch.h"
 
 namespace sspcg {
@@ -37,13 +39,141 @@ __device__ inline void stnt(T* p, T v)
     __builtin_nontemporal_store(v, p);
 }
 
+// RR consecutive rows of one column: one 16-byte vector when RR > 1.
+template <typename T, int RR>
+struct Rows {
+    T v[RR];
+};
+
+template <typename T, int RR>
+__device__ inline Rows<T, RR> ld_rows(const T* p)
+{
+    Rows<T, RR> o;
+    if constexpr (RR == 1) {
+        o.v[0] = ldnt(p);
+    } else {
+        typedef T VT __attribute__((ext_vector_type(RR)));
+        const VT w = ldnt(reinterpret_cast<const VT*>(p));
+#pragma unroll
+        for (int e = 0; e < RR; ++e) o.v[e] = w[e];
+    }
+    return o;
+}
+
+template <typename T, int RR>
+__device__ inline void st_rows(T* p, const Rows<T, RR>& o)
+{
+    if constexpr (RR == 1) {
+        stnt(p, o.v[0]);
+    } else {
+        typedef T VT __attribute__((ext_vector_type(RR)));
+        VT w;
+#pragma unroll
+        for (int e = 0; e < RR; ++e) w[e] = o.v[e];
+        stnt(reinterpret_cast<VT*>(p), w);
+    }
+}
+
+// Rows i .. i+RR-1 of the block update and their Gram terms (see
+// k_update_gram).  Every load of the rows is issued before the first store
+// (the wait counter is shared by loads and stores, so a load queued behind a
+// store also waits for the store): 271 -> 217 us per FP32 update at 192^3,
+// 420 -> 407 us per FP64 update with one row per thread.  The rows' terms
+// are added to acc in row order.
+template <int S, typename T, int MODE, int RR, int K>
+__device__ inline void update_rows(int64_t i, int64_t ld, const T* __restrict__ Z,
+                                   T* __restrict__ Q, const T* __restrict__ AZ,
+                                   T* __restrict__ AQ, const double* __restrict__ beta,
+                                   const T* __restrict__ r, T* __restrict__ x,
+                                   const double (&al)[S], bool pend, double (&acc)[K])
+{
+    Rows<T, RR> zv[S], azv[S];
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+        zv[j] = ld_rows<T, RR>(Z + j * ld + i);
+        azv[j] = ld_rows<T, RR>(AZ + j * ld + i);
+    }
+    const Rows<T, RR> rv = ld_rows<T, RR>(r + i);
+    double q[S][RR], aq[S][RR];
+    if constexpr (MODE == 0) {
+#pragma unroll
+        for (int j = 0; j < S; ++j) {
+            st_rows<T, RR>(Q + j * ld + i, zv[j]);
+            st_rows<T, RR>(AQ + j * ld + i, azv[j]);
+#pragma unroll
+            for (int e = 0; e < RR; ++e) {
+                q[j][e] = (double)zv[j].v[e];
+                aq[j][e] = (double)azv[j].v[e];
+            }
+        }
+    } else {
+        Rows<T, RR> qo[S], aqo[S], xi;
+#pragma unroll
+        for (int j = 0; j < S; ++j) {
+            qo[j] = ld_rows<T, RR>(Q + j * ld + i);
+            aqo[j] = ld_rows<T, RR>(AQ + j * ld + i);
+        }
+        if constexpr (MODE == 2) xi = ld_rows<T, RR>(x + i);
+        Rows<T, RR> qn[S], aqn[S];
+#pragma unroll
+        for (int j = 0; j < S; ++j)
+#pragma unroll
+            for (int e = 0; e < RR; ++e) {
+                double tq = 0.0, taq = 0.0;
+#pragma unroll
+                for (int l = 0; l < S; ++l) {
+                    tq = fma((double)qo[l].v[e], beta[l * S + j], tq);
+                    taq = fma((double)aqo[l].v[e], beta[l * S + j], taq);
+                }
+                qn[j].v[e] = (T)((double)zv[j].v[e] + tq);
+                aqn[j].v[e] = (T)((double)azv[j].v[e] + taq);
+                q[j][e] = (double)qn[j].v[e];
+                aq[j][e] = (double)aqn[j].v[e];
+            }
+#pragma unroll
+        for (int j = 0; j < S; ++j) {
+            st_rows<T, RR>(Q + j * ld + i, qn[j]);
+            st_rows<T, RR>(AQ + j * ld + i, aqn[j]);
+        }
+        if constexpr (MODE == 2) {
+            // a select, not a branch, so the load of x stays with the
+            // others; without a pending update x is written back as read
+            Rows<T, RR> xo;
+#pragma unroll
+            for (int e = 0; e < RR; ++e) {
+                double qa = 0.0;
+#pragma unroll
+                for (int j = 0; j < S; ++j) qa = fma((double)qo[j].v[e], al[j], qa);
+                xo.v[e] = pend ? (T)((double)xi.v[e] + qa) : xi.v[e];
+            }
+            st_rows<T, RR>(x + i, xo);
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < RR; ++e) {
+        int k = 0;
+#pragma unroll
+        for (int a = 0; a < S; ++a)
+#pragma unroll
+            for (int b = 0; b <= a; ++b) {
+                acc[k] = fma(q[a][e], aq[b][e], acc[k]);
+                ++k;
+            }
+        const double ri = (double)rv.v[e];
+#pragma unroll
+        for (int a = 0; a < S; ++a) acc[K - S + a] = fma(q[a][e], ri, acc[K - S + a]);
+    }
+}
+
 // MODE 0: the first update (Q = Z, AQ = AZ).  MODE 1: Q = Z + Q beta,
 // AQ = AZ + AQ beta.  MODE 2: MODE 1 and, if ctrl->x_pending, the x update of
 // the previous outer iteration, x += Q alpha with the old Q streamed here
 // anyway, in the same arithmetic as k_xr; the solve's x/r update then
 // leaves x alone and never reads Q.  x is loaded with the row's other
-// operands, so its latency overlaps theirs.
-template <int S, typename T, int MODE>
+// operands, so its latency overlaps theirs.  R consecutive rows per thread
+// as one 16-byte vector per column when the columns allow it (the rows of
+// a ragged tail one by one), else R = 1.
+template <int S, typename T, int MODE, int R>
 __global__ __launch_bounds__(kRowBlock) void k_update_gram(int64_t n, int64_t ld,
                                                            const T* __restrict__ Z,
                                                            T* __restrict__ Q,
@@ -58,10 +188,6 @@ __global__ __launch_bounds__(kRowBlock) void k_update_gram(int64_t n, int64_t ld
 {
     if (ctrl && ctrl->done) return;
     constexpr int K = S * (S + 1) / 2 + S;
-    double acc[K];
-#pragma unroll
-    for (int e = 0; e < K; ++e) acc[e] = 0.0;
-    constexpr bool FIRST = MODE == 0;
     bool pend = false;
     double al[S];
     if constexpr (MODE == 2) {
@@ -69,96 +195,26 @@ __global__ __launch_bounds__(kRowBlock) void k_update_gram(int64_t n, int64_t ld
 #pragma unroll
         for (int j = 0; j < S; ++j) al[j] = alpha[j];
     }
-    const int64_t ntiles = (n + kRowBlock - 1) / kRowBlock;
-    const TileRange tr = xcd_tiles(ntiles);
-    for (int64_t t = tr.first; t < tr.end; t += tr.step) {
-        const int64_t i = t * kRowBlock + threadIdx.x;
-        if (i >= n) break;
-        // Every load of the row is issued before its first store (the wait
-        // counter is shared by loads and stores, so a load queued behind a
-        // store also waits for the store): 271 -> 217 us per FP32 update at
-        // 192^3, 420 -> 407 us per FP64 update (all operands held at once
-        // cost a wave per SIMD, but the loads are in flight together).
-        constexpr bool kPreload = true;
-        double q[S], aq[S];
-        T zv[S], azv[S];
-        T rv = (T)0;
-        if constexpr (kPreload) {
+    constexpr int64_t kRows = (int64_t)kRowBlock * R;
+    const int64_t ntiles = (n + kRows - 1) / kRows;
+    const int VB = virtual_blocks(ntiles);
+    for (int v = blockIdx.x; v < VB; v += gridDim.x) {
+        double acc[K];
 #pragma unroll
-            for (int j = 0; j < S; ++j) {
-                zv[j] = ldnt(Z + j * ld + i);
-                azv[j] = ldnt(AZ + j * ld + i);
-            }
-            rv = ldnt(r + i);
-        }
-        if constexpr (FIRST) {
-#pragma unroll
-            for (int j = 0; j < S; ++j) {
-                const T zj = kPreload ? zv[j] : ldnt(Z + j * ld + i);
-                const T azj = kPreload ? azv[j] : ldnt(AZ + j * ld + i);
-                stnt(Q + j * ld + i, zj);
-                stnt(AQ + j * ld + i, azj);
-                q[j] = (double)zj;
-                aq[j] = (double)azj;
-            }
-        } else {
-            double qo[S], aqo[S];
-#pragma unroll
-            for (int j = 0; j < S; ++j) {
-                qo[j] = (double)ldnt(Q + j * ld + i);
-                aqo[j] = (double)ldnt(AQ + j * ld + i);
-            }
-            T xi = (T)0;
-            if constexpr (MODE == 2) xi = ldnt(x + i);
-            T qn[S], aqn[S];
-#pragma unroll
-            for (int j = 0; j < S; ++j) {
-                double tq = 0.0, taq = 0.0;
-#pragma unroll
-                for (int l = 0; l < S; ++l) {
-                    tq = fma(qo[l], beta[l * S + j], tq);
-                    taq = fma(aqo[l], beta[l * S + j], taq);
-                }
-                const T zj = kPreload ? zv[j] : ldnt(Z + j * ld + i);
-                const T azj = kPreload ? azv[j] : ldnt(AZ + j * ld + i);
-                qn[j] = (T)((double)zj + tq);
-                aqn[j] = (T)((double)azj + taq);
-                q[j] = (double)qn[j];
-                aq[j] = (double)aqn[j];
-                if constexpr (!kPreload) {
-                    stnt(Q + j * ld + i, qn[j]);
-                    stnt(AQ + j * ld + i, aqn[j]);
-                }
-            }
-            if constexpr (kPreload) {
-#pragma unroll
-                for (int j = 0; j < S; ++j) {
-                    stnt(Q + j * ld + i, qn[j]);
-                    stnt(AQ + j * ld + i, aqn[j]);
-                }
-            }
-            if constexpr (MODE == 2) {
-                // a select, not a branch, so the load of x stays with the
-                // others; without a pending update x is written back as read
-                double qa = 0.0;
-#pragma unroll
-                for (int j = 0; j < S; ++j) qa = fma(qo[j], al[j], qa);
-                stnt(x + i, pend ? (T)((double)xi + qa) : xi);
+        for (int e = 0; e < K; ++e) acc[e] = 0.0;
+        const TileRange tr = vblock_tiles(ntiles, VB, v);
+        for (int64_t t = tr.first; t < tr.end; t += tr.step) {
+            const int64_t i = t * kRows + (int64_t)threadIdx.x * R;
+            if (i >= n) break;
+            if (R == 1 || i + R <= n) {
+                update_rows<S, T, MODE, R, K>(i, ld, Z, Q, AZ, AQ, beta, r, x, al, pend, acc);
+            } else {
+                for (int64_t k = i; k < n; ++k)
+                    update_rows<S, T, MODE, 1, K>(k, ld, Z, Q, AZ, AQ, beta, r, x, al, pend, acc);
             }
         }
-        const double ri = (double)(kPreload ? rv : ldnt(r + i));
-        int e = 0;
-#pragma unroll
-        for (int a = 0; a < S; ++a)
-#pragma unroll
-            for (int b = 0; b <= a; ++b) {
-                acc[e] = fma(q[a], aq[b], acc[e]);
-                ++e;
-            }
-#pragma unroll
-        for (int a = 0; a < S; ++a) acc[K - S + a] = fma(q[a], ri, acc[K - S + a]);
+        block_partials<K, kRowBlock>(acc, partials, v, VB);
     }
-    block_partials<K, kRowBlock>(acc, partials);
 }
 
 // R consecutive rows per thread, read as one R-wide vector per column (the
@@ -185,43 +241,47 @@ __global__ __launch_bounds__(kRowBlock) void k_gram_rect(int64_t n, int64_t ld,
     };
     constexpr int64_t kRows = (int64_t)kRowBlock * R;
     const int64_t ntiles = (n + kRows - 1) / kRows;
-    const TileRange tr = xcd_tiles(ntiles);
-    for (int64_t t = tr.first; t < tr.end; t += tr.step) {
-        const int64_t i = t * kRows + (int64_t)threadIdx.x * R;
-        if (i >= n) break;
-        if constexpr (R > 1) {
-            if (i + R <= n) {
-                typedef T VT __attribute__((ext_vector_type(R)));
-                VT qv[S], azv[S];
-#pragma unroll
-                for (int j = 0; j < S; ++j) {
-                    qv[j] = ldnt(reinterpret_cast<const VT*>(Q + j * ld + i));
-                    azv[j] = ldnt(reinterpret_cast<const VT*>(AZ + j * ld + i));
-                }
-#pragma unroll
-                for (int e = 0; e < R; ++e) {
-                    double q[S], az[S];
+    const int VB = virtual_blocks(ntiles);
+    for (int v = blockIdx.x; v < VB; v += gridDim.x) {
+        zero_acc(acc);
+        const TileRange tr = vblock_tiles(ntiles, VB, v);
+        for (int64_t t = tr.first; t < tr.end; t += tr.step) {
+            const int64_t i = t * kRows + (int64_t)threadIdx.x * R;
+            if (i >= n) break;
+            if constexpr (R > 1) {
+                if (i + R <= n) {
+                    typedef T VT __attribute__((ext_vector_type(R)));
+                    VT qv[S], azv[S];
 #pragma unroll
                     for (int j = 0; j < S; ++j) {
-                        q[j] = (double)qv[j][e];
-                        az[j] = (double)azv[j][e];
+                        qv[j] = ldnt(reinterpret_cast<const VT*>(Q + j * ld + i));
+                        azv[j] = ldnt(reinterpret_cast<const VT*>(AZ + j * ld + i));
                     }
-                    add_row(q, az);
-                }
-                continue;
-            }
-        }
-        for (int e = 0; e < R && i + e < n; ++e) {
-            double q[S], az[S];
 #pragma unroll
-            for (int j = 0; j < S; ++j) {
-                q[j] = (double)ldnt(Q + j * ld + i + e);
-                az[j] = (double)ldnt(AZ + j * ld + i + e);
+                    for (int e = 0; e < R; ++e) {
+                        double q[S], az[S];
+#pragma unroll
+                        for (int j = 0; j < S; ++j) {
+                            q[j] = (double)qv[j][e];
+                            az[j] = (double)azv[j][e];
+                        }
+                        add_row(q, az);
+                    }
+                    continue;
+                }
             }
-            add_row(q, az);
+            for (int e = 0; e < R && i + e < n; ++e) {
+                double q[S], az[S];
+#pragma unroll
+                for (int j = 0; j < S; ++j) {
+                    q[j] = (double)ldnt(Q + j * ld + i + e);
+                    az[j] = (double)ldnt(AZ + j * ld + i + e);
+                }
+                add_row(q, az);
+            }
         }
+        block_partials<K, kRowBlock>(acc, partials, v, VB);
     }
-    block_partials<K, kRowBlock>(acc, partials);
 }
 
 // R consecutive rows per thread as R-wide vectors (R = 16 bytes / element
@@ -244,71 +304,75 @@ __global__ __launch_bounds__(kRowBlock) void k_xr(int64_t n, int64_t ld, const T
     double acc[1] = {0.0};
     constexpr int64_t kRows = (int64_t)kRowBlock * R;
     const int64_t ntiles = (n + kRows - 1) / kRows;
-    const TileRange tr = xcd_tiles(ntiles);
-    for (int64_t t = tr.first; t < tr.end; t += tr.step) {
-        const int64_t i = t * kRows + (int64_t)threadIdx.x * R;
-        if (i >= n) break;
-        if constexpr (R > 1) {
-            if (i + R <= n) {
-                typedef T VT __attribute__((ext_vector_type(R)));
-                double aqa[R];
+    const int VB = virtual_blocks(ntiles);
+    for (int v = blockIdx.x; v < VB; v += gridDim.x) {
+        zero_acc(acc);
+        const TileRange tr = vblock_tiles(ntiles, VB, v);
+        for (int64_t t = tr.first; t < tr.end; t += tr.step) {
+            const int64_t i = t * kRows + (int64_t)threadIdx.x * R;
+            if (i >= n) break;
+            if constexpr (R > 1) {
+                if (i + R <= n) {
+                    typedef T VT __attribute__((ext_vector_type(R)));
+                    double aqa[R];
 #pragma unroll
-                for (int e = 0; e < R; ++e) aqa[e] = 0.0;
-#pragma unroll
-                for (int j = 0; j < S; ++j) {
-                    const VT aq = ldnt(reinterpret_cast<const VT*>(AQ + j * ld + i));
-#pragma unroll
-                    for (int e = 0; e < R; ++e) aqa[e] = fma((double)aq[e], al[j], aqa[e]);
-                }
-                if (x) {
-                    double qa[R];
-#pragma unroll
-                    for (int e = 0; e < R; ++e) qa[e] = 0.0;
+                    for (int e = 0; e < R; ++e) aqa[e] = 0.0;
 #pragma unroll
                     for (int j = 0; j < S; ++j) {
-                        const VT q = ldnt(reinterpret_cast<const VT*>(Q + j * ld + i));
+                        const VT aq = ldnt(reinterpret_cast<const VT*>(AQ + j * ld + i));
 #pragma unroll
-                        for (int e = 0; e < R; ++e) qa[e] = fma((double)q[e], al[j], qa[e]);
+                        for (int e = 0; e < R; ++e) aqa[e] = fma((double)aq[e], al[j], aqa[e]);
                     }
-                    VT xv = *reinterpret_cast<const VT*>(x + i);
+                    if (x) {
+                        double qa[R];
 #pragma unroll
-                    for (int e = 0; e < R; ++e) xv[e] = (T)((double)xv[e] + qa[e]);
-                    *reinterpret_cast<VT*>(x + i) = xv;
+                        for (int e = 0; e < R; ++e) qa[e] = 0.0;
+#pragma unroll
+                        for (int j = 0; j < S; ++j) {
+                            const VT q = ldnt(reinterpret_cast<const VT*>(Q + j * ld + i));
+#pragma unroll
+                            for (int e = 0; e < R; ++e) qa[e] = fma((double)q[e], al[j], qa[e]);
+                        }
+                        VT xv = *reinterpret_cast<const VT*>(x + i);
+#pragma unroll
+                        for (int e = 0; e < R; ++e) xv[e] = (T)((double)xv[e] + qa[e]);
+                        *reinterpret_cast<VT*>(x + i) = xv;
+                    }
+                    VT rv = *reinterpret_cast<const VT*>(r + i);
+#pragma unroll
+                    for (int e = 0; e < R; ++e) rv[e] = (T)((double)rv[e] - aqa[e]);
+                    *reinterpret_cast<VT*>(r + i) = rv;
+                    if (z1) {
+                        const VT dv = ldnt(reinterpret_cast<const VT*>(dinv + i));
+                        VT zv;
+#pragma unroll
+                        for (int e = 0; e < R; ++e) zv[e] = (T)((double)dv[e] * (double)rv[e]);
+                        stnt(reinterpret_cast<VT*>(z1 + i), zv);
+                    }
+#pragma unroll
+                    for (int e = 0; e < R; ++e) acc[0] = fma((double)rv[e], (double)rv[e], acc[0]);
+                    continue;
                 }
-                VT rv = *reinterpret_cast<const VT*>(r + i);
+            }
+            for (int e = 0; e < R && i + e < n; ++e) {
+                const int64_t k = i + e;
+                double aqa = 0.0;
 #pragma unroll
-                for (int e = 0; e < R; ++e) rv[e] = (T)((double)rv[e] - aqa[e]);
-                *reinterpret_cast<VT*>(r + i) = rv;
-                if (z1) {
-                    const VT dv = ldnt(reinterpret_cast<const VT*>(dinv + i));
-                    VT zv;
+                for (int j = 0; j < S; ++j) aqa = fma((double)ldnt(AQ + j * ld + k), al[j], aqa);
+                if (x) {
+                    double qa = 0.0;
 #pragma unroll
-                    for (int e = 0; e < R; ++e) zv[e] = (T)((double)dv[e] * (double)rv[e]);
-                    stnt(reinterpret_cast<VT*>(z1 + i), zv);
+                    for (int j = 0; j < S; ++j) qa = fma((double)ldnt(Q + j * ld + k), al[j], qa);
+                    x[k] = (T)((double)x[k] + qa);
                 }
-#pragma unroll
-                for (int e = 0; e < R; ++e) acc[0] = fma((double)rv[e], (double)rv[e], acc[0]);
-                continue;
+                const T rk = (T)((double)r[k] - aqa);
+                r[k] = rk;
+                if (z1) stnt(z1 + k, (T)((double)ldnt(dinv + k) * (double)rk));
+                acc[0] = fma((double)rk, (double)rk, acc[0]);
             }
         }
-        for (int e = 0; e < R && i + e < n; ++e) {
-            const int64_t k = i + e;
-            double aqa = 0.0;
-#pragma unroll
-            for (int j = 0; j < S; ++j) aqa = fma((double)ldnt(AQ + j * ld + k), al[j], aqa);
-            if (x) {
-                double qa = 0.0;
-#pragma unroll
-                for (int j = 0; j < S; ++j) qa = fma((double)ldnt(Q + j * ld + k), al[j], qa);
-                x[k] = (T)((double)x[k] + qa);
-            }
-            const T rk = (T)((double)r[k] - aqa);
-            r[k] = rk;
-            if (z1) stnt(z1 + k, (T)((double)ldnt(dinv + k) * (double)rk));
-            acc[0] = fma((double)rk, (double)rk, acc[0]);
-        }
+        block_partials<1, kRowBlock>(acc, partials, v, VB);
     }
-    block_partials<1, kRowBlock>(acc, partials);
 }
 
 template <typename T>
@@ -360,8 +424,13 @@ template <typename K>
 static int block_grid(int64_t n, K kernel, int blocks_per_cu = 8)
 {
     const int resident = resident_blocks(reinterpret_cast<const void*>(kernel), kRowBlock);
-    return persistent_grid((n + kRowBlock - 1) / kRowBlock, blocks_per_cu, resident);
+    const int64_t ntiles = (n + kRowBlock - 1) / kRowBlock;
+    return std::min(persistent_grid(ntiles, blocks_per_cu, resident), virtual_blocks(ntiles));
 }
+
+// Partial sums a reduction over `units` threads' worth of rows writes: one
+// per virtual block (common.h), however many workgroups ran.
+static int reduce_slots(int64_t units) { return virtual_blocks((units + kRowBlock - 1) / kRowBlock); }
 
 #define SSPCG_S_CASES(X) \
     X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16)
@@ -371,32 +440,42 @@ int launch_update_gram(int64_t n, int s, const T* Z, T* Q, const T* AZ, T* AQ, c
                        const T* r, T* x, const double* alpha, int64_t ld, double* partials,
                        int* G_out, const Ctrl* ctrl, hipStream_t st)
 {
+    // FP32: four rows per thread as 16-byte vectors when every column allows
+    // it (217 -> 202 us at 192^3).  FP64 keeps one row per thread: two rows
+    // as 16-byte vectors measured the same (402-411 vs 407-409 us); the
+    // kernel already streams at the rate a copy or triad reaches on these
+    // boxes for its mix of reads and writes (12 of 37 columns written).
+    constexpr int RV = sizeof(T) == 4 ? 4 : 1;
+    auto a16 = [](const void* p) { return p == nullptr || reinterpret_cast<uintptr_t>(p) % 16 == 0; };
+    const bool vec = RV > 1 && ld % RV == 0 && a16(Z) && a16(Q) && a16(AZ) && a16(AQ) && a16(r) &&
+                     a16(x);
+    const int64_t units = vec ? (n + RV - 1) / RV : n;
+    const int mode = !beta ? 0 : (!x || !ctrl) ? 1 : 2;
     int G = 0;
     switch (s) {
+#define L(S, M, R)                                                                               \
+    do {                                                                                         \
+        G = block_grid(units, k_update_gram<S, T, M, R>);                                       \
+        hipLaunchKernelGGL((k_update_gram<S, T, M, R>), dim3(G), dim3(kRowBlock), 0, st, n, ld,  \
+                           Z, Q, AZ, AQ, beta, r, x, alpha, partials, ctrl);                     \
+    } while (0)
 #define X(S)                                                                                    \
     case S:                                                                                     \
-        if (!beta) {                                                                            \
-            G = block_grid(n, k_update_gram<S, T, 0>);                                          \
-            hipLaunchKernelGGL((k_update_gram<S, T, 0>), dim3(G), dim3(kRowBlock), 0, st, n, ld, \
-                               Z, Q, AZ, AQ, beta, r, x, alpha, partials, ctrl);                \
-        } else if (!x || !ctrl) {                                                               \
-            G = block_grid(n, k_update_gram<S, T, 1>);                                          \
-            hipLaunchKernelGGL((k_update_gram<S, T, 1>), dim3(G), dim3(kRowBlock), 0, st, n, ld, \
-                               Z, Q, AZ, AQ, beta, r, x, alpha, partials, ctrl);                \
+        if (vec) {                                                                              \
+            if (mode == 0) L(S, 0, RV); else if (mode == 1) L(S, 1, RV); else L(S, 2, RV);      \
         } else {                                                                                \
-            G = block_grid(n, k_update_gram<S, T, 2>);                                          \
-            hipLaunchKernelGGL((k_update_gram<S, T, 2>), dim3(G), dim3(kRowBlock), 0, st, n, ld, \
-                               Z, Q, AZ, AQ, beta, r, x, alpha, partials, ctrl);                \
+            if (mode == 0) L(S, 0, 1); else if (mode == 1) L(S, 1, 1); else L(S, 2, 1);         \
         }                                                                                       \
         break;
         SSPCG_S_CASES(X)
 #undef X
+#undef L
     default:
         set_error("s out of range");
         return SSPCG_ERR_ARG;
     }
     SSPCG_LAUNCHED("k_update_gram");
-    *G_out = G;
+    *G_out = reduce_slots(units);
     return SSPCG_OK;
 }
 
@@ -435,7 +514,7 @@ int launch_gram_rect(int64_t n, int s, const T* Q, const T* AZ, int64_t ld, doub
         return SSPCG_ERR_ARG;
     }
     SSPCG_LAUNCHED("k_gram_rect");
-    *G_out = G;
+    *G_out = reduce_slots(units);
     return SSPCG_OK;
 }
 
@@ -469,7 +548,7 @@ int launch_xr(int64_t n, int s, const T* Q, const T* AQ, const double* alpha, in
         return SSPCG_ERR_ARG;
     }
     SSPCG_LAUNCHED("k_xr");
-    *G_out = G;
+    *G_out = reduce_slots(units);
     return SSPCG_OK;
 }
 

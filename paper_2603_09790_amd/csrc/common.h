@@ -152,6 +152,39 @@ __device__ inline TileRange xcd_tiles(int64_t ntiles)
     return {b, ntiles, G};
 }
 
+// Reductions group their rows by "virtual blocks": VB(ntiles) groups of
+// tiles, a number that depends on the problem size only.  The workgroups of
+// a launch -- as many as fit, which depends on the kernel's register use --
+// walk the virtual blocks (workgroup b takes b, b + G, ...), and every
+// virtual block writes its own partial sums, so the sums and their rounding
+// do not depend on the grid: a change of occupancy or of compiler leaves the
+// results, and the iterations built on them, the same bit for bit.  Virtual
+// block v takes the tiles xcd_tiles would give workgroup v of a grid of VB,
+// so with G a multiple of 8 every workgroup stays on the die of its tiles.
+// 512 at most: at 192^3 the s-step iteration took 2.024 ms with 512, 2.027
+// with 1024 and 2.044 with 2048 (each virtual block ends in a block-wide
+// reduction, and the single-workgroup finish sums VB values); contiguous
+// chunks per virtual block instead of strided tiles made the block update
+// 20-40 % slower.
+constexpr int kVirtualBlocks = 512;
+
+__host__ __device__ inline int virtual_blocks(int64_t ntiles)
+{
+    const int64_t v = ntiles < kVirtualBlocks ? ntiles : kVirtualBlocks;
+    if (v >= kNumXcd) return (int)(v - v % kNumXcd);
+    return (int)(v > 0 ? v : 1);
+}
+
+__device__ inline TileRange vblock_tiles(int64_t ntiles, int VB, int v)
+{
+    if (VB >= kNumXcd && VB % kNumXcd == 0) {
+        const int x = v % kNumXcd, j = v / kNumXcd, per = VB / kNumXcd;
+        const int64_t lo = ntiles * x / kNumXcd, hi = ntiles * (x + 1) / kNumXcd;
+        return {lo + j, hi, per};
+    }
+    return {v, ntiles, VB};
+}
+
 // Tile of a non-persistent launch (one tile per workgroup, grid = ntiles):
 // the first 8*floor(ntiles/8) tiles are split into 8 contiguous ranges, one
 // per die, walked in dispatch order; the remaining tiles map to themselves.
@@ -163,6 +196,13 @@ __device__ inline int64_t xcd_block_tile()
     return (b % kNumXcd) * (full / kNumXcd) + b / kNumXcd;
 }
 
+template <int K>
+__device__ inline void zero_acc(double (&a)[K])
+{
+#pragma unroll
+    for (int e = 0; e < K; ++e) a[e] = 0.0;
+}
+
 __device__ inline double wave_sum(double v)
 {
 #pragma unroll
@@ -171,24 +211,28 @@ __device__ inline double wave_sum(double v)
 }
 
 // Reduces K per-thread accumulators over the block in a fixed order and
-// writes the block's partial sums to partials[k * G + blockIdx.x].
+// writes the partial sums of virtual block v to partials[k * VB + v].  Every
+// thread of the block must call it; it may be called again for the next
+// virtual block (the trailing barrier frees the shared staging).
 template <int K, int NT>
-__device__ inline void block_partials(double (&acc)[K], double* __restrict__ partials)
+__device__ inline void block_partials(double (&acc)[K], double* __restrict__ partials, int v,
+                                      int VB)
 {
     __shared__ double sm[NT / kWave][K > 0 ? K : 1];
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-        const double v = wave_sum(acc[k]);
-        if (lane == 0) sm[wave][k] = v;
+        const double s = wave_sum(acc[k]);
+        if (lane == 0) sm[wave][k] = s;
     }
     __syncthreads();
     for (int k = threadIdx.x; k < K; k += NT) {
         double s = 0.0;
 #pragma unroll
         for (int w = 0; w < NT / kWave; ++w) s += sm[w][k];
-        partials[(int64_t)k * gridDim.x + blockIdx.x] = s;
+        partials[(int64_t)k * VB + v] = s;
     }
+    __syncthreads();
 }
 
 // Sum of partials[e * G + 0 .. G-1] by one wavefront in a fixed order.

@@ -20,6 +20,8 @@
 #include <cmath>
 #include <cstring>
 
+#include <algorithm>
+
 #include "launch.h"
 
 namespace sspcg {
@@ -31,12 +33,16 @@ __global__ __launch_bounds__(kRowBlock) void k_iv_norm0(int64_t n, const double*
 {
     double acc[1] = {0.0};
     const int64_t ntiles = (n + kRowBlock - 1) / kRowBlock;
-    const TileRange tr = xcd_tiles(ntiles);
-    for (int64_t t = tr.first; t < tr.end; t += tr.step) {
-        const int64_t i = t * kRowBlock + threadIdx.x;
-        if (i < n) acc[0] = fma(v0[i], v0[i], acc[0]);
+    const int VB = virtual_blocks(ntiles);
+    for (int v = blockIdx.x; v < VB; v += gridDim.x) {
+        zero_acc(acc);
+        const TileRange tr = vblock_tiles(ntiles, VB, v);
+        for (int64_t t = tr.first; t < tr.end; t += tr.step) {
+            const int64_t i = t * kRowBlock + threadIdx.x;
+            if (i < n) acc[0] = fma(v0[i], v0[i], acc[0]);
+        }
+        block_partials<1, kRowBlock>(acc, partials, v, VB);
     }
-    block_partials<1, kRowBlock>(acc, partials);
 }
 
 // First vector: v_1 = v0 / ||v0|| (power) or y_1 = D^{-1/2} v_1 (Lanczos,
@@ -107,17 +113,21 @@ __global__ __launch_bounds__(kRowBlock) void k_lz_orth(int64_t n, int j, int ste
     const double bp = j > 0 ? coef[steps + j - 1] : 0.0;
     double acc[1] = {0.0};
     const int64_t ntiles = (n + kRowBlock - 1) / kRowBlock;
-    const TileRange tr = xcd_tiles(ntiles);
-    for (int64_t t = tr.first; t < tr.end; t += tr.step) {
-        const int64_t i = t * kRowBlock + threadIdx.x;
-        if (i < n) {
-            const double di = dinv[i];
-            const double w = di * q[i] - a * y[i] - bp * yp[i];
-            yp[i] = w;
-            acc[0] = fma(w, w / di, acc[0]);
+    const int VB = virtual_blocks(ntiles);
+    for (int v = blockIdx.x; v < VB; v += gridDim.x) {
+        zero_acc(acc);
+        const TileRange tr = vblock_tiles(ntiles, VB, v);
+        for (int64_t t = tr.first; t < tr.end; t += tr.step) {
+            const int64_t i = t * kRowBlock + threadIdx.x;
+            if (i < n) {
+                const double di = dinv[i];
+                const double w = di * q[i] - a * y[i] - bp * yp[i];
+                yp[i] = w;
+                acc[0] = fma(w, w / di, acc[0]);
+            }
         }
+        block_partials<1, kRowBlock>(acc, partials, v, VB);
     }
-    block_partials<1, kRowBlock>(acc, partials);
 }
 
 // beta_j = ||w||; y_{j+1} = w / beta_j in place.  Block 0 records the step
@@ -167,16 +177,20 @@ __global__ __launch_bounds__(kRowBlock) void k_pw_apply(int64_t n, double* __res
     if (ctrl->done) return;
     double acc[1] = {0.0};
     const int64_t ntiles = (n + kRowBlock - 1) / kRowBlock;
-    const TileRange tr = xcd_tiles(ntiles);
-    for (int64_t t = tr.first; t < tr.end; t += tr.step) {
-        const int64_t i = t * kRowBlock + threadIdx.x;
-        if (i < n) {
-            const double w = dinv[i] * q[i];
-            q[i] = w;
-            acc[0] = fma(w, w, acc[0]);
+    const int VB = virtual_blocks(ntiles);
+    for (int v = blockIdx.x; v < VB; v += gridDim.x) {
+        zero_acc(acc);
+        const TileRange tr = vblock_tiles(ntiles, VB, v);
+        for (int64_t t = tr.first; t < tr.end; t += tr.step) {
+            const int64_t i = t * kRowBlock + threadIdx.x;
+            if (i < n) {
+                const double w = dinv[i] * q[i];
+                q[i] = w;
+                acc[0] = fma(w, w, acc[0]);
+            }
         }
+        block_partials<1, kRowBlock>(acc, partials, v, VB);
     }
-    block_partials<1, kRowBlock>(acc, partials);
 }
 
 // Power step j: lambda_j = ||w||, v = w / lambda_j.  Block 0 keeps the
@@ -329,11 +343,13 @@ int run_interval(const sspcg_matrix* A, int method, int steps, double rtol, cons
     SSPCG_HIP(hipMemcpyAsync(ctrl, &c, sizeof(Ctrl), hipMemcpyHostToDevice, st));
     SSPCG_HIP(hipStreamSynchronize(st));
 
-    const int Gr = row_grid(n);
+    // reductions over the rows write one partial per virtual block (common.h)
+    const int VBr = virtual_blocks((n + kRowBlock - 1) / kRowBlock);
+    const int Gr = std::min(row_grid(n), VBr);
     hipLaunchKernelGGL(k_iv_norm0, dim3(Gr), dim3(kRowBlock), 0, st, n, v0, part2);
     SSPCG_LAUNCHED("k_iv_norm0");
     hipLaunchKernelGGL(k_iv_start, dim3(Gr), dim3(kRowBlock), 0, st, n, lanczos ? 1 : 0, v0,
-                       A->dinv, part2, Gr, y, yp, ctrl);
+                       A->dinv, part2, VBr, y, yp, ctrl);
     SSPCG_LAUNCHED("k_iv_start");
     for (int j = 0; j < max_iter; ++j) {
         int G = 0;
@@ -344,7 +360,7 @@ int run_interval(const sspcg_matrix* A, int method, int steps, double rtol, cons
                                A->dinv, part, G, part2, coef, ctrl);
             SSPCG_LAUNCHED("k_lz_orth");
             hipLaunchKernelGGL(k_lz_next, dim3(Gr), dim3(kRowBlock), 0, st, n, j, steps, yp, part2,
-                               Gr, coef, ctrl);
+                               VBr, coef, ctrl);
             SSPCG_LAUNCHED("k_lz_next");
             std::swap(y, yp);
         } else {
@@ -352,7 +368,7 @@ int run_interval(const sspcg_matrix* A, int method, int steps, double rtol, cons
                                ctrl);
             SSPCG_LAUNCHED("k_pw_apply");
             hipLaunchKernelGGL(k_pw_next, dim3(Gr), dim3(kRowBlock), 0, st, n, j, rtol, y, q, part2,
-                               Gr, ctrl);
+                               VBr, ctrl);
             SSPCG_LAUNCHED("k_pw_next");
         }
     }

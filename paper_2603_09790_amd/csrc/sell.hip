@@ -26,6 +26,8 @@
 #include <unordered_map>
 #include <vector>
 
+#include <cstdlib>
+
 #include "launch.h"
 
 namespace sspcg {
@@ -666,41 +668,44 @@ __global__ __launch_bounds__(kRowBlock) void k_residual(Sell<double> A, const do
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
     constexpr int kSlicesPerTile = kRowBlock / kSlice;
     const int64_t ntiles = (A.nslices + kSlicesPerTile - 1) / kSlicesPerTile;
-    const TileRange tr = xcd_tiles(ntiles);
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    extern __shared__ __attribute__((aligned(16))) double lds_dyn[];
-    for (int64_t t = tr.first; t < tr.end; t += tr.step) {
-        const int64_t c = t * kSlicesPerTile + wave;
-        double ax = 0.0;
-        if constexpr (STAGED) {
-            // every wave of the workgroup reaches both barriers of every tile
-            __syncthreads();
-            stage_x<double>(A, t * kRowBlock, x, lds_dyn);
-            __syncthreads();
-            if (c >= A.nslices) continue;
-            double dg;
-            ax = uniform_row_lds<double>(A, c, lane, (int)threadIdx.x, lds_dyn, dg);
-        } else {
-            if (c >= A.nslices) break;
-            ax = slice_row<double>(A, c, lane, x);
-        }
-        const int64_t row = c * kSlice + lane;
-        if (row < A.n) {
-            const double bi = b[row];
-            const double ri = bi - ax;
-            const TR rs = (TR)ri;
-            r[row] = rs;
-            acc[0] = fma(ri, ri, acc[0]);
-            acc[1] = fma((double)rs, (double)rs, acc[1]);
-            acc[2] = fma(bi, bi, acc[2]);
-            if (z1) {
-                const TR zs = (TR)((double)dinvT[row] * (double)rs);
-                z1[row] = zs;
-                acc[3] = fma((double)rs, (double)zs, acc[3]);
+    const int VB = virtual_blocks(ntiles);
+    for (int v = blockIdx.x; v < VB; v += gridDim.x) {
+        const TileRange tr = vblock_tiles(ntiles, VB, v);
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        extern __shared__ __attribute__((aligned(16))) double lds_dyn[];
+        for (int64_t t = tr.first; t < tr.end; t += tr.step) {
+            const int64_t c = t * kSlicesPerTile + wave;
+            double ax = 0.0;
+            if constexpr (STAGED) {
+                // every wave of the workgroup reaches both barriers of every tile
+                __syncthreads();
+                stage_x<double>(A, t * kRowBlock, x, lds_dyn);
+                __syncthreads();
+                if (c >= A.nslices) continue;
+                double dg;
+                ax = uniform_row_lds<double>(A, c, lane, (int)threadIdx.x, lds_dyn, dg);
+            } else {
+                if (c >= A.nslices) break;
+                ax = slice_row<double>(A, c, lane, x);
+            }
+            const int64_t row = c * kSlice + lane;
+            if (row < A.n) {
+                const double bi = b[row];
+                const double ri = bi - ax;
+                const TR rs = (TR)ri;
+                r[row] = rs;
+                acc[0] = fma(ri, ri, acc[0]);
+                acc[1] = fma((double)rs, (double)rs, acc[1]);
+                acc[2] = fma(bi, bi, acc[2]);
+                if (z1) {
+                    const TR zs = (TR)((double)dinvT[row] * (double)rs);
+                    z1[row] = zs;
+                    acc[3] = fma((double)rs, (double)zs, acc[3]);
+                }
             }
         }
+        block_partials<4, kRowBlock>(acc, partials, v, VB);
     }
-    block_partials<4, kRowBlock>(acc, partials);
 }
 
 template <bool STAGED>
@@ -713,6 +718,9 @@ __global__ __launch_bounds__(kRowBlock) void k_pcg_spmv(Sell<double> A, const do
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
     constexpr int kSlicesPerTile = kRowBlock / kSlice;
     const int64_t ntiles = (A.nslices + kSlicesPerTile - 1) / kSlicesPerTile;
+    // classical PCG keeps one partial per workgroup: its iteration count
+    // does not hinge on rounding the way two FGS sweeps do, and the loop over
+    // virtual blocks costs its SpMV registers (127 -> 156) and 10 % of time
     const TileRange tr = xcd_tiles(ntiles);
     double acc[1] = {0.0};
     extern __shared__ __attribute__((aligned(16))) double lds_dyn[];
@@ -739,7 +747,7 @@ __global__ __launch_bounds__(kRowBlock) void k_pcg_spmv(Sell<double> A, const do
             acc[0] = fma(prow, ap, acc[0]);
         }
     }
-    block_partials<1, kRowBlock>(acc, partials);
+    block_partials<1, kRowBlock>(acc, partials, blockIdx.x, gridDim.x);
 }
 
 // Classical PCG update, iteration k: alpha = rho_k / p^T q (every block sums
@@ -778,7 +786,7 @@ __global__ __launch_bounds__(kRowBlock) void k_pcg_update(int64_t n, int64_t k, 
             acc[1] = fma(ri, ri, acc[1]);
         }
     }
-    block_partials<2, kRowBlock>(acc, partials);
+    block_partials<2, kRowBlock>(acc, partials, blockIdx.x, gridDim.x);
 }
 
 // p = z + (rho_{k+1} / rho_k) p, after the stop test of iteration k.  Every
@@ -913,8 +921,22 @@ void plan_lds(sspcg_matrix* A)
     A->lds_n = ncl * w;
 }
 
+// SSPCG_GRID_BLOCKS_PER_CU=k in the environment (read once per process)
+// caps every persistent grid at k workgroups per CU: a debugging aid that
+// shows the s-step results do not depend on the grid (virtual blocks).
+static int grid_cap_from_env()
+{
+    static const int cap = [] {
+        const char* v = std::getenv("SSPCG_GRID_BLOCKS_PER_CU");
+        const int k = v ? std::atoi(v) : 0;
+        return k > 0 ? k : 1 << 20;
+    }();
+    return cap;
+}
+
 int persistent_grid(int64_t ntiles, int blocks_per_cu, int resident)
 {
+    blocks_per_cu = std::min(blocks_per_cu, grid_cap_from_env());
     int64_t g = (int64_t)num_cus() * std::min(blocks_per_cu, resident);
     g = std::min<int64_t>(g, kMaxGrid);
     g = std::min<int64_t>(g, std::max<int64_t>(ntiles, 1));
@@ -980,10 +1002,17 @@ static int64_t spmv_tiles(const sspcg_matrix* A)
 // Persistent grid for the SpMV kernels that also reduce: all workgroups
 // resident at once.
 template <typename K>
-static int spmv_reduce_grid(const sspcg_matrix* A, K kernel, size_t dyn_lds)
+static int spmv_persistent_grid(const sspcg_matrix* A, K kernel, size_t dyn_lds)
 {
     const int resident = resident_blocks(reinterpret_cast<const void*>(kernel), kRowBlock, dyn_lds);
     return persistent_grid(spmv_tiles(A), 8, resident);
+}
+
+// A reduction's grid never exceeds its virtual blocks (common.h).
+template <typename K>
+static int spmv_reduce_grid(const sspcg_matrix* A, K kernel, size_t dyn_lds)
+{
+    return std::min(spmv_persistent_grid(A, kernel, dyn_lds), virtual_blocks(spmv_tiles(A)));
 }
 
 // Dynamic LDS of the SpMV kernels: the staged windows of x.
@@ -1215,7 +1244,7 @@ int launch_residual(const sspcg_matrix* A, const double* x, const double* b, TR*
                            z1, dinvT, partials);
     }
     SSPCG_LAUNCHED("k_residual");
-    *G_out = G;
+    *G_out = virtual_blocks(spmv_tiles(A));
     return SSPCG_OK;
 }
 
@@ -1231,11 +1260,11 @@ int launch_pcg_spmv(const sspcg_matrix* A, const double* p, double* q, double* p
     const size_t lds = lds_bytes<double>(A);
     int G;
     if (S.lds_n > 0) {
-        G = spmv_reduce_grid(A, k_pcg_spmv<true>, lds);
+        G = spmv_persistent_grid(A, k_pcg_spmv<true>, lds);
         hipLaunchKernelGGL((k_pcg_spmv<true>), dim3(G), dim3(kRowBlock), lds, st, S, p, q, partials,
                            ctrl);
     } else {
-        G = spmv_reduce_grid(A, k_pcg_spmv<false>, lds);
+        G = spmv_persistent_grid(A, k_pcg_spmv<false>, lds);
         hipLaunchKernelGGL((k_pcg_spmv<false>), dim3(G), dim3(kRowBlock), lds, st, S, p, q,
                            partials, ctrl);
     }

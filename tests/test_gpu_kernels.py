@@ -737,3 +737,30 @@ def test_many_offset_runs(nruns, full):
     xo, ro = oracle.sspcg(A, b, s=4, sweeps=3, interval=interval, tol=1e-30, max_outer=12)
     assert ig["outer_iters"] == ro["iters"] == 12
     assert np.linalg.norm(host(xg) - xo) <= 1e-10 * np.linalg.norm(xo)
+
+
+@pytest.mark.parametrize("n", [4099, 4096])
+def test_update_gram_row_groups_match_single_rows(n):
+    """FP32 block update: with 16-byte aligned columns four rows per thread
+    (the rows of a ragged tail one by one), otherwise one row per thread
+    (ld not a multiple of 4).  Q and AQ are the same bits either way; W and
+    b1 only sum the rows in another order."""
+    s = 6
+    rng = np.random.default_rng(31)
+    beta = gpu(rng.normal(size=(s, s)) * 0.3)
+    cols = [rng.normal(size=(s, n)).astype(np.float32) for _ in range(4)]
+    r = rng.normal(size=n).astype(np.float32)
+    out = []
+    for ld in (P.leading_dim(n), n + 1 if n % 4 == 0 else n + 2):
+        Z, Q, AZ, AQ = (torch.zeros((s, ld), dtype=torch.float32, device=DEV) for _ in range(4))
+        for t, c in zip((Z, Q, AZ, AQ), cols):
+            t[:, :n] = gpu(c)
+        W, b1 = P.block_update_gram(n, Z, Q, AZ, AQ, beta, gpu(r))
+        out.append((host(Q)[:, :n], host(AQ)[:, :n], host(W), host(b1)))
+    (q0, aq0, w0, b0), (q1, aq1, w1, b1_) = out
+    assert np.array_equal(q0, q1) and np.array_equal(aq0, aq1)
+    Qd, AQd = q0.astype(float), aq0.astype(float)
+    gram_close(w0, w1, Qd, AQd, tol=1e-13)
+    gram_close(b0[:, None], b1_[:, None], Qd, r.astype(float)[None, :], tol=1e-13)
+    Wr, br = oracle.gram(q0, aq0, r)
+    gram_close(w0, Wr, Qd, AQd)

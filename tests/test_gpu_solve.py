@@ -376,6 +376,40 @@ def test_debug_sync_mode():
     assert np.array_equal(np.load("/tmp/sspcg_debug_sync_x.npy"), x.cpu().numpy())
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_results_do_not_depend_on_the_grid(precision):
+    """Reductions write one partial per virtual block, a count fixed by the
+    problem size: a solve whose persistent grids are capped at one workgroup
+    per CU (SSPCG_GRID_BLOCKS_PER_CU=1, in a child process; 256 workgroups
+    for 512 virtual blocks at 64^3) gives the same iterates bit for bit as the
+    default grids."""
+    import os
+    import subprocess
+    import sys
+    out_path = f"/tmp/sspcg_grid_x_{precision}.npy"
+    code = (
+        "import numpy as np, torch, paper_2603_09790_amd as P, sspcg_inputs as si\n"
+        "A = si.stencil('27pt', 64, si.coeff_blocks(64))\n"
+        "M = P.Matrix.from_csr(A, fp32=True, device='cuda:0')\n"
+        "b = torch.from_numpy(si.rhs_normal(A.n))\n"
+        f"x, i = P.solve(M, b, s=6, sweeps=2, interval=si.lanczos_bounds(A), tol=1e-10, "
+        f"precision='{precision}')\n"
+        f"np.save('{out_path}', x.cpu().numpy())\n"
+        "print(i['status'], i['outer_iters'])\n")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    env = dict(os.environ, SSPCG_GRID_BLOCKS_PER_CU="1", PYTHONPATH=root)
+    out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True,
+                         timeout=240, cwd=root)
+    assert out.returncode == 0, out.stderr[-2000:]
+    st, iters = map(int, out.stdout.split()[-2:])
+    A = si.stencil("27pt", 64, si.coeff_blocks(64))
+    M = P.Matrix.from_csr(A, fp32=True, device=DEV)
+    x, info = P.solve(M, gpu(si.rhs_normal(A.n)), s=6, sweeps=2, interval=si.lanczos_bounds(A),
+                      tol=1e-10, precision=precision)
+    assert st == 0 and iters == info["outer_iters"]
+    assert np.array_equal(np.load(out_path), x.cpu().numpy())
+
+
 def test_monomial_basis_solve(poisson7):
     w = poisson7
     x, info = run(w, s=4, sweeps=2, basis="monomial", tol=1e-30, max_outer=10)
