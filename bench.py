@@ -651,6 +651,48 @@ def seed_spread(P, torch, dev, args, nseeds=5):
             **{k: stats(k) for k in ("fp64_s", "fp64_outer", "mixed_s", "mixed_inner", "speedup")}}
 
 
+def oracle_times_small(w, gpu_outer, reps=3):
+    """The oracle's 2D Poisson 64^2 solve (s = 4, nu = 2, 1e-8) on one host
+    thread and on all of them: median wall time of `reps` solves each."""
+    import oracle
+    oracle.build()
+    full = os.cpu_count() or 1
+    out = {"host": host_description(), "gpu_outer_iters": gpu_outer}
+    for k in (1, full):
+        oracle.set_threads(k)
+        ts = []
+        for _ in range(reps):
+            t0 = time.time()
+            _, r = oracle.sspcg(w["A"], w["b"], s=4, sweeps=2, interval=w["interval"], tol=1e-8)
+            ts.append(time.time() - t0)
+        out[f"threads_{k}"] = {"seconds": float(np.median(ts)), "outer_iters": r["iters"]}
+    oracle.set_threads(full)
+    return out
+
+
+def oracle_per_outer(w, gpu_outer, sample=10):
+    """The oracle's 7-point 128^3 s = 4, nu = 2 iteration on one host thread
+    and on all of them: seconds per outer iteration from the difference of a
+    (2 + sample)- and a 2-iteration run (setup excluded), and that times the
+    GPU's outer-iteration count."""
+    import oracle
+    oracle.build()
+    full = os.cpu_count() or 1
+    out = {"host": host_description(), "gpu_outer_iters": gpu_outer, "sample_outer": sample}
+    for k in (1, full):
+        oracle.set_threads(k)
+        ts = []
+        for m in (2, 2 + sample):
+            t0 = time.time()
+            oracle.sspcg(w["A"], w["b"], s=4, sweeps=2, interval=w["interval"], tol=1e-30,
+                         max_outer=m)
+            ts.append(time.time() - t0)
+        per = (ts[1] - ts[0]) / sample
+        out[f"threads_{k}"] = {"seconds_per_outer": per, "scaled_to_gpu_count": per * gpu_outer}
+    oracle.set_threads(full)
+    return out
+
+
 def other_configs(P, torch, dev, args):
     """Times the other standard workloads (their parity is in the tests):
     2D Poisson 64^2 (launch-latency bound), 7-point Poisson 128^3 over s and
@@ -676,6 +718,8 @@ def other_configs(P, torch, dev, args):
         res[name]["us_per_iter"] = 1e3 * res[name]["time_ms"] / max(res[name]["iters"], 1)
     out["poisson5_64"] = res
     log(f"[configs] poisson5 64^2: {res}")
+    out["poisson5_64"]["oracle"] = oracle_times_small(w, res["sspcg"]["iters"])
+    log(f"[configs] poisson5 64^2 oracle: {out['poisson5_64']['oracle']}")
     # 7-point Poisson 128^3 grid of s and sweeps
     w = si.workload("poisson7")
     M = P.Matrix.from_csr(w["A"], device=dev)
@@ -690,6 +734,8 @@ def other_configs(P, torch, dev, args):
                                      "status": i["status_name"]}
     out["poisson7_128"] = {"interval": list(w["interval"]), "runs": grid}
     log(f"[configs] poisson7 128^3: {grid}")
+    out["poisson7_128"]["oracle_s4_nu2"] = oracle_per_outer(w, grid["s4_nu2"]["outer_iters"])
+    log(f"[configs] poisson7 128^3 oracle: {out['poisson7_128']['oracle_s4_nu2']}")
     # mixed to 1e-10 on the benchmark system, error against an FP64 solve at 1e-12
     A, b_np, interval = build_workload(192)
     M = P.Matrix.from_csr(A, fp32=True, device=dev)

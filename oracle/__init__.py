@@ -63,6 +63,7 @@ def lib():
     sig = {
         "or_version": (_I, []),
         "or_threads": (_I, []),
+        "or_set_threads": (None, [_I]),
         "or_dot": (_D, [_I64, _P, _P]),
         "or_nrm2": (_D, [_I64, _P]),
         "or_spmv": (None, [_I64, _P, _P, _P, _P, _P]),
@@ -118,6 +119,11 @@ def _f32(a) -> np.ndarray:
 
 def threads() -> int:
     return lib().or_threads()
+
+
+def set_threads(k: int) -> None:
+    """Threads the oracle's row loops may use from now on (k >= 1)."""
+    lib().or_set_threads(int(k))
 
 
 def dot(a, b) -> float:

@@ -54,6 +54,16 @@ typedef struct {
 
 int or_version(void) { return 1; }
 
+/* Sets the number of threads the row loops may use (k >= 1). */
+void or_set_threads(int k)
+{
+#ifdef _OPENMP
+    if (k >= 1) omp_set_num_threads(k);
+#else
+    (void)k;
+#endif
+}
+
 int or_threads(void)
 {
 #ifdef _OPENMP
