@@ -181,7 +181,7 @@ def main() -> int:
     ap.add_argument("--no-profile", action="store_true",
                     help="time without the per-phase HIP events")
     ap.add_argument("--mode", choices=["solve", "kernels", "paper", "configs", "seeds",
-                                       "traffic-record", "trace-summary"],
+                                       "traffic-record", "trace-summary", "units-summary"],
                     default="solve",
                     help="kernels: a few launches of each hot kernel on the workload and a "
                          "copy kernel of known size (for rocprofv3 counter passes); paper: the "
@@ -193,6 +193,8 @@ def main() -> int:
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--trace-dir", default="gpurun_out/prof_bench",
                     help="trace-summary: output directory of a rocprofv3 --kernel-trace run")
+    ap.add_argument("--units-dirs", nargs=2, default=["gpurun_out/pmc_k1", "gpurun_out/pmc_k2"],
+                    help="units-summary: output directories of the two unit-counter passes")
     ap.add_argument("--fetch-dir", default="gpurun_out/pmc_FETCH_SIZE",
                     help="traffic-record: output directory of the rocprofv3 --pmc FETCH_SIZE pass")
     ap.add_argument("--write-dir", default="gpurun_out/pmc_WRITE_SIZE",
@@ -200,6 +202,9 @@ def main() -> int:
     args = ap.parse_args()
     if args.mode == "trace-summary":
         print(trace_summary(args.trace_dir))
+        return 0
+    if args.mode == "units-summary":
+        print(units_summary(args.units_dirs[0], args.units_dirs[1]))
         return 0
     if args.mode == "traffic-record":
         # host only: turns two counter passes over --mode kernels into the
@@ -547,6 +552,43 @@ def trace_summary(outdir: str, min_pct: float = 0.01) -> str:
             continue
         lines.append(f"| `{k}` | {len(v)} | {sum(v) / 1e6:.2f} | {np.mean(v) / 1e3:.1f} | "
                      f"{min(v) / 1e3:.1f} | {max(v) / 1e3:.1f} | {pct:.2f} |")
+    return "\n".join(lines)
+
+
+UNIT_KERNELS = ["k_spmv<double, 0>", "k_spmv<double, 1>", "k_spmv<double, 2>",
+                "k_spmv<float, 0>", "k_update_gram<6, double, 1, 1>", "k_gram_rect<6, double, 2>",
+                "k_xr<6, double, 2>"]
+
+
+def units_summary(k1_dir: str, k2_dir: str) -> str:
+    """Markdown table of the unit counters of the hot kernels (two passes over
+    --mode kernels).  Fractions are unit-busy cycles over the kernel's cycles
+    (SQ_CYCLES per shader engine, 32 engines) and the 256 CUs' units; counts
+    are per wavefront."""
+    c = {}
+    for d, names in ((k1_dir, ["TA_TA_BUSY_sum", "TA_ADDR_STALLED_BY_TC_CYCLES_sum",
+                               "TCP_PENDING_STALL_CYCLES_sum", "TCP_TCC_READ_REQ_sum"]),
+                     (k2_dir, ["TCC_HIT_sum", "TCC_MISS_sum", "SQ_CYCLES", "SQ_WAVES",
+                               "SQ_INSTS_VMEM_RD", "SQ_INSTS_LDS", "SQ_INSTS_VALU"])):
+        for nm in names:
+            for k, v in counter_rows(d, nm).items():
+                c.setdefault(k, {})[nm] = v
+    cus, ses = 256, 32
+    lines = ["| kernel | TA busy | TA stalled by L1 | L1 pending-miss stall | vector-memory loads / wave "
+             "| LDS instr / wave | VALU / wave | L2 hit rate |",
+             "|---|---:|---:|---:|---:|---:|---:|---:|"]
+    for k in UNIT_KERNELS:
+        v = c.get(k)
+        if not v or "SQ_CYCLES" not in v or "TA_TA_BUSY_sum" not in v:
+            continue
+        cyc = v["SQ_CYCLES"] / ses
+        waves = max(v["SQ_WAVES"], 1.0)
+        hit = v["TCC_HIT_sum"] / max(v["TCC_HIT_sum"] + v["TCC_MISS_sum"], 1.0)
+        lines.append(f"| `{k}` | {v['TA_TA_BUSY_sum'] / cus / cyc:.2f} | "
+                     f"{v['TA_ADDR_STALLED_BY_TC_CYCLES_sum'] / max(v['TA_TA_BUSY_sum'], 1):.2f} | "
+                     f"{v['TCP_PENDING_STALL_CYCLES_sum'] / cus / cyc:.2f} | "
+                     f"{v['SQ_INSTS_VMEM_RD'] / waves:.1f} | {v['SQ_INSTS_LDS'] / waves:.1f} | "
+                     f"{v['SQ_INSTS_VALU'] / waves:.0f} | {hit:.2f} |")
     return "\n".join(lines)
 
 
