@@ -76,17 +76,21 @@ struct Sell {
     int32_t usym;               // uniform: symmetric half storage
     int32_t uo[32];             // uniform: the global offset list, in the kernel arguments
     // LDS staging of x (uniform layout): the gathers x[row + o_k] of a
-    // 256-row tile starting at row a fall into one window per run of
-    // consecutive offsets (o, o+1, ...): x[a + lo .. a + lo + lds_w), lo the
-    // run's first offset rounded down to even, lds_w (even) >= 256 + the
-    // run's span + that rounding for every run.  Each workgroup copies its
-    // windows to LDS slots of lds_w elements with contiguous loads, then
-    // reads entry k of tile row t at sx[lds_k[k] + t].  lds_n = 0: gathers
-    // from memory (more than kMaxWindows runs, or the layout is not uniform).
-    int32_t lds_n;              // staged elements per tile (ncl * lds_w)
-    int32_t ncl, lds_w;         // runs (windows), LDS slot length
+    // 256-row tile starting at row a fall into windows of x, one per run of
+    // consecutive offsets (o, o+1, ...), runs less than a tile apart sharing
+    // one: window j is x[a + cl_lo[j] .. a + cl_lo[j] + cl_len[j]), cl_lo[j]
+    // its first offset rounded down to even, cl_len[j] (even) >= 256 + the
+    // span of its offsets, stored at sx[cl_base[j] ..).  Each workgroup
+    // copies its windows to LDS with contiguous loads, then reads entry k of
+    // tile row t at sx[lds_k[k] + t].  lds_n = 0: gathers from memory (more
+    // than kMaxWindows windows, a window longer than the copy covers, or the
+    // layout is not uniform).
+    int32_t lds_n;              // staged elements per tile (the sum of cl_len)
+    int32_t ncl;                // windows
     int32_t lds_self;           // LDS index of x[row] for tile row 0 (the offset 0)
-    int32_t cl_lo[32];          // first offset of each window (even)
+    int32_t cl_lo[12];          // window j: first offset (even),
+    int32_t cl_len[12];         //   length (even),
+    int32_t cl_base[12];        //   first LDS element (even)
     int32_t lds_k[32];          // LDS index of entry k for tile row 0 (stored pads: any window)
     int64_t nslices;
     const int64_t* slice_ptr;   // nslices + 1 slot offsets, multiples of 64
@@ -100,8 +104,11 @@ struct Sell {
 // Longest shared offset list a slice may use (the offsets travel in kernel
 // arguments for the uniform layout).
 constexpr int kMaxUnion = 32;
-constexpr int kMaxWindows = 12;    // LDS windows of x per tile at most (about 27 KB in FP64)
+constexpr int kMaxWindows = 12;    // LDS windows of x per tile at most
+constexpr int kStageRounds = 2;    // element pairs each thread copies per window at most
+constexpr int kMaxStaged = 4096;   // staged elements per tile at most (32 KB in FP64)
 static_assert(sizeof(Sell<double>::uo) == kMaxUnion * sizeof(int32_t), "offset list size");
+static_assert(sizeof(Sell<double>::cl_lo) == kMaxWindows * sizeof(int32_t), "window list size");
 
 // Grid of a persistent row kernel: at most `blocks_per_cu` workgroups per CU
 // and never more than fit at once (`resident`, from the occupancy of the

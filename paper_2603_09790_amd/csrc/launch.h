@@ -19,8 +19,8 @@ struct sspcg_matrix {
     int32_t usym = 0;                   // uniform layout: symmetric half storage
     int32_t* uoff = nullptr;
     int32_t uoff_host[32] = {};         // the same list, copied into kernel arguments
-    int32_t lds_n = 0, ncl = 0, lds_w = 0, lds_self = 0;   // LDS staging of x (see Sell)
-    int32_t cl_lo[32] = {}, lds_k[32] = {};
+    int32_t lds_n = 0, ncl = 0, lds_self = 0;   // LDS staging of x (see Sell)
+    int32_t cl_lo[12] = {}, cl_len[12] = {}, cl_base[12] = {}, lds_k[32] = {};
     double* sval = nullptr;
     float* sval32 = nullptr;
     double* dinv = nullptr;

@@ -446,26 +446,21 @@ __device__ inline double uniform_row(const Sell<T>& A, int64_t c, int lane, cons
 // ---- uniform layout with x staged in LDS (Sell::lds_n > 0)
 
 // Copies the tile's windows of x to LDS (all threads of the workgroup; the
-// caller synchronizes).  Windows start at even offsets and all have the even
-// length lds_w, and tiles start at multiples of 256 rows, so every window is
-// a run of element pairs 16-byte aligned in x (when x is) and in LDS: each
-// thread moves a pair per load.  Half of the workgroup copies window 2m and
-// the other half window 2m + 1 (elements 0..255); one more load per thread
-// covers the few elements past 256 of every window.  All loads are issued
-// before the first store.  Elements outside [0, n) are staged as 0: the
-// entries that would read them are stored zeros.
+// caller synchronizes).  Windows start at even offsets and have even
+// lengths, and tiles start at multiples of 256 rows, so every window is a
+// run of element pairs, 16-byte aligned in x (when x is) and in LDS: thread
+// t moves pairs t and t + 256 of each window.  Windows are taken four at a
+// time, all loads of a group issued before its first store (the 27-point
+// stencil has three windows, one plane each).  The window index is the same
+// for all lanes, so the window bounds stay scalar.  Elements outside [0, n)
+// are staged as 0: the entries that would read them are stored zeros.
 template <typename T>
 __device__ inline void stage_x(const Sell<T>& A, int64_t a, const T* __restrict__ x,
                                T* __restrict__ sx)
 {
     typedef T T2 __attribute__((ext_vector_type(2)));
-    constexpr int kHalf = kRowBlock / 2;
-    constexpr int kRounds = (kMaxWindows + 1) / 2;
+    constexpr int kGroup = 4;
     const int t = threadIdx.x;
-    // the half is the same for all lanes of a wave: keep it (and the window
-    // index) scalar, so the window offsets are scalar loads of the kernel
-    // arguments rather than vector loads that stall the staging
-    const int half = __builtin_amdgcn_readfirstlane(t) / kHalf, u = t % kHalf;
     const bool x16 = reinterpret_cast<uintptr_t>(x) % (2 * sizeof(T)) == 0;
     auto load2 = [&](int64_t g) {
         T2 v;
@@ -477,36 +472,24 @@ __device__ inline void stage_x(const Sell<T>& A, int64_t a, const T* __restrict_
         }
         return v;
     };
-    T2 head[kRounds];
+    for (int j0 = 0; j0 < A.ncl; j0 += kGroup) {
+        T2 v[kGroup][kStageRounds];
 #pragma unroll
-    for (int m = 0; m < kRounds; ++m) {
-        const int j = 2 * m + half;
-        head[m] = (T2)((T)0);
-        if (j < A.ncl) head[m] = load2(a + A.cl_lo[j] + 2 * u);
-    }
-    // pairs kHalf .. lds_w/2 - 1 of the windows, one per thread (the plan
-    // keeps ncl * tp <= 256)
-    const int tp = A.lds_w / 2 - kHalf;
-    const bool has_tail = t < A.ncl * tp;
-    int tj = 0, tq = 0;
-    T2 tail = (T2)((T)0);
-    if (has_tail) {
-        tj = t / tp;
-        tq = t - tj * tp;
-        // per-lane window: select among the scalar offsets (a select of the
-        // loads themselves would become one vector load at a selected address)
-        int lo = __builtin_amdgcn_readfirstlane(A.cl_lo[0]);
+        for (int g = 0; g < kGroup; ++g)
 #pragma unroll
-        for (int j = 1; j < kMaxWindows; ++j)
-            lo = tj == j ? __builtin_amdgcn_readfirstlane(A.cl_lo[j]) : lo;
-        tail = load2(a + lo + kRowBlock + 2 * tq);
-    }
+            for (int r = 0; r < kStageRounds; ++r) {
+                const int j = j0 + g, e = 2 * (t + r * kRowBlock);
+                if (j < A.ncl && e < A.cl_len[j]) v[g][r] = load2(a + A.cl_lo[j] + e);
+            }
 #pragma unroll
-    for (int m = 0; m < kRounds; ++m) {
-        const int j = 2 * m + half;
-        if (j < A.ncl) *reinterpret_cast<T2*>(sx + j * A.lds_w + 2 * u) = head[m];
+        for (int g = 0; g < kGroup; ++g)
+#pragma unroll
+            for (int r = 0; r < kStageRounds; ++r) {
+                const int j = j0 + g, e = 2 * (t + r * kRowBlock);
+                if (j < A.ncl && e < A.cl_len[j])
+                    *reinterpret_cast<T2*>(sx + A.cl_base[j] + e) = v[g][r];
+            }
     }
-    if (has_tail) *reinterpret_cast<T2*>(sx + tj * A.lds_w + kRowBlock + 2 * tq) = tail;
 }
 
 // Full storage, x from LDS: entry k of tile row t multiplies sx[lds_k[k] + t]
@@ -887,38 +870,49 @@ int resident_blocks(const void* kernel, int threads, size_t dyn_lds)
 
 void plan_lds(sspcg_matrix* A)
 {
-    A->lds_n = A->ncl = A->lds_w = 0;
+    A->lds_n = A->ncl = 0;
     if (!A->uniform || A->uw < 1) return;
     const int32_t* o = A->uoff_host;
-    int j = -1;
-    int run[kMaxUnion], last[kMaxUnion];
+    for (int k = 1; k < A->uw; ++k)
+        if (o[k] <= o[k - 1]) return;   // the list is ascending by construction
+    // runs of consecutive offsets, merged while the next starts at most one
+    // tile after the current window's last offset: one window then costs no
+    // more LDS and fewer loads than two (the 27-point stencil's three runs
+    // of a plane, N apart, share one window when N <= 256)
+    int lo[kMaxUnion], hi[kMaxUnion], win[kMaxUnion];
+    int nw = 0;
     for (int k = 0; k < A->uw; ++k) {
-        if (k == 0 || o[k] != o[k - 1] + 1) A->cl_lo[++j] = o[k];
-        last[j] = o[k];
-        run[k] = j;
+        if (nw == 0 || o[k] - hi[nw - 1] > kRowBlock) {
+            lo[nw] = hi[nw] = o[k];
+            ++nw;
+        } else {
+            hi[nw - 1] = o[k];
+        }
+        win[k] = nw - 1;
     }
-    const int ncl = j + 1;
-    if (ncl > kMaxWindows) return;   // too many windows: gathers from memory
-    // windows start at even offsets (rounded down) and share an even length,
-    // so they are staged as aligned pairs of elements
-    int w = 0;
-    for (int r = 0; r < ncl; ++r) {
-        A->cl_lo[r] &= ~1;
-        w = std::max(w, kRowBlock + last[r] - A->cl_lo[r]);
+    if (nw > kMaxWindows) return;   // too many windows: gathers from memory
+    int base = 0;
+    for (int j = 0; j < nw; ++j) {
+        const int l = lo[j] & ~1;   // even: windows are copied as aligned pairs
+        int len = hi[j] + kRowBlock - l;
+        len += len & 1;
+        if (len > 2 * kStageRounds * kRowBlock) return;   // longer than the copy covers
+        A->cl_lo[j] = l;
+        A->cl_len[j] = len;
+        A->cl_base[j] = base;
+        base += len;
     }
-    w += w & 1;
-    if (w > 2 * kRowBlock) return;   // a run longer than the tile: not worth staging
-    if (ncl * (w / 2 - kRowBlock / 2) > kRowBlock) return;   // tails: one pair per thread
-    for (int k = 0; k < A->uw; ++k) A->lds_k[k] = run[k] * w + (o[k] - A->cl_lo[run[k]]);
-    for (int k = A->uw; k < kMaxUnion; ++k) A->lds_k[k] = A->lds_k[A->uw - 1];
-    // the element x[row] itself, for the epilogue of the matrix powers kernel
+    if (base > kMaxStaged) return;
     A->lds_self = -1;
-    for (int k = 0; k < A->uw; ++k)
+    for (int k = 0; k < A->uw; ++k) {
+        A->lds_k[k] = A->cl_base[win[k]] + (o[k] - A->cl_lo[win[k]]);
+        // the element x[row] itself, for the epilogue of the matrix powers kernel
         if (o[k] == 0) A->lds_self = A->lds_k[k];
+    }
+    for (int k = A->uw; k < kMaxUnion; ++k) A->lds_k[k] = A->lds_k[A->uw - 1];
     if (A->lds_self < 0) return;   // no diagonal offset (cannot happen: the diagonal is stored)
-    A->ncl = ncl;
-    A->lds_w = w;
-    A->lds_n = ncl * w;
+    A->ncl = nw;
+    A->lds_n = base;
 }
 
 // SSPCG_GRID_BLOCKS_PER_CU=k in the environment (read once per process)
@@ -966,9 +960,10 @@ static Sell<T> make_view(const sspcg_matrix* A, int uwv, const T* val, const T* 
     // memory (124 vs 181 us at 192^3, 27 points)
     S.lds_n = sizeof(T) == 8 ? A->lds_n : 0;
     S.ncl = A->ncl;
-    S.lds_w = A->lds_w;
     S.lds_self = A->lds_self;
-    std::copy(A->cl_lo, A->cl_lo + kMaxUnion, S.cl_lo);
+    std::copy(A->cl_lo, A->cl_lo + kMaxWindows, S.cl_lo);
+    std::copy(A->cl_len, A->cl_len + kMaxWindows, S.cl_len);
+    std::copy(A->cl_base, A->cl_base + kMaxWindows, S.cl_base);
     std::copy(A->lds_k, A->lds_k + kMaxUnion, S.lds_k);
     S.nslices = A->nslices;
     S.slice_ptr = A->slice_ptr;
