@@ -79,18 +79,18 @@ struct Sell {
     // 256-row tile starting at row a fall into windows of x, one per run of
     // consecutive offsets (o, o+1, ...), runs less than a tile apart sharing
     // one: window j is x[a + cl_lo[j] .. a + cl_lo[j] + cl_len[j]), cl_lo[j]
-    // its first offset rounded down to even, cl_len[j] (even) >= 256 + the
-    // span of its offsets, stored at sx[cl_base[j] ..).  Each workgroup
-    // copies its windows to LDS with contiguous loads, then reads entry k of
-    // tile row t at sx[lds_k[k] + t].  lds_n = 0: gathers from memory (more
-    // than kMaxWindows windows, a window longer than the copy covers, or the
-    // layout is not uniform).
+    // its first offset rounded down to a multiple of 4, cl_len[j] (a multiple
+    // of 4) >= 256 + the span of its offsets, stored at sx[cl_base[j] ..).
+    // Each workgroup copies its windows to LDS with contiguous loads, then
+    // reads entry k of tile row t at sx[lds_k[k] + t].  lds_n = 0: gathers
+    // from memory (more than kMaxWindows windows, a window longer than the
+    // copy covers, or the layout is not uniform).
     int32_t lds_n;              // staged elements per tile (the sum of cl_len)
     int32_t ncl;                // windows
     int32_t lds_self;           // LDS index of x[row] for tile row 0 (the offset 0)
-    int32_t cl_lo[12];          // window j: first offset (even),
-    int32_t cl_len[12];         //   length (even),
-    int32_t cl_base[12];        //   first LDS element (even)
+    int32_t cl_lo[12];          // window j: first offset,
+    int32_t cl_len[12];         //   length,
+    int32_t cl_base[12];        //   first LDS element (all multiples of 4)
     int32_t lds_k[32];          // LDS index of entry k for tile row 0 (stored pads: any window)
     int64_t nslices;
     const int64_t* slice_ptr;   // nslices + 1 slot offsets, multiples of 64

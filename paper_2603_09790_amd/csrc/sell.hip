@@ -446,48 +446,50 @@ __device__ inline double uniform_row(const Sell<T>& A, int64_t c, int lane, cons
 // ---- uniform layout with x staged in LDS (Sell::lds_n > 0)
 
 // Copies the tile's windows of x to LDS (all threads of the workgroup; the
-// caller synchronizes).  Windows start at even offsets and have even
-// lengths, and tiles start at multiples of 256 rows, so every window is a
-// run of element pairs, 16-byte aligned in x (when x is) and in LDS: thread
-// t moves pairs t and t + 256 of each window.  Windows are taken four at a
-// time, all loads of a group issued before its first store (the 27-point
-// stencil has three windows, one plane each).  The window index is the same
-// for all lanes, so the window bounds stay scalar.  Elements outside [0, n)
-// are staged as 0: the entries that would read them are stored zeros.
+// caller synchronizes).  Windows start at offsets that are multiples of 4
+// and have lengths that are multiples of 4, and tiles start at multiples of
+// 256 rows, so every window is a run of 16-byte vectors (2 FP64 or 4 FP32
+// elements), aligned in x (when x is) and in LDS: thread t moves vectors
+// t and t + 256 of each window.  Windows are taken four at a time, all loads
+// of a group issued before its first store (the 27-point stencil has three
+// windows, one plane each).  The window index is the same for all lanes, so
+// the window bounds stay scalar.  Elements outside [0, n) are staged as 0:
+// the entries that would read them are stored zeros.
 template <typename T>
 __device__ inline void stage_x(const Sell<T>& A, int64_t a, const T* __restrict__ x,
                                T* __restrict__ sx)
 {
-    typedef T T2 __attribute__((ext_vector_type(2)));
+    constexpr int V = 16 / sizeof(T);
+    typedef T TV __attribute__((ext_vector_type(V)));
     constexpr int kGroup = 4;
     const int t = threadIdx.x;
-    const bool x16 = reinterpret_cast<uintptr_t>(x) % (2 * sizeof(T)) == 0;
-    auto load2 = [&](int64_t g) {
-        T2 v;
-        if (x16 && g >= 0 && g + 1 < A.n) {
-            v = *reinterpret_cast<const T2*>(x + g);
+    const bool x16 = reinterpret_cast<uintptr_t>(x) % 16 == 0;
+    auto loadv = [&](int64_t g) {
+        TV v;
+        if (x16 && g >= 0 && g + V <= A.n) {
+            v = *reinterpret_cast<const TV*>(x + g);
         } else {
-            v.x = (g >= 0 && g < A.n) ? x[g] : (T)0;
-            v.y = (g + 1 >= 0 && g + 1 < A.n) ? x[g + 1] : (T)0;
+#pragma unroll
+            for (int h = 0; h < V; ++h) v[h] = (g + h >= 0 && g + h < A.n) ? x[g + h] : (T)0;
         }
         return v;
     };
     for (int j0 = 0; j0 < A.ncl; j0 += kGroup) {
-        T2 v[kGroup][kStageRounds];
+        TV v[kGroup][kStageRounds];
 #pragma unroll
         for (int g = 0; g < kGroup; ++g)
 #pragma unroll
             for (int r = 0; r < kStageRounds; ++r) {
-                const int j = j0 + g, e = 2 * (t + r * kRowBlock);
-                if (j < A.ncl && e < A.cl_len[j]) v[g][r] = load2(a + A.cl_lo[j] + e);
+                const int j = j0 + g, e = V * (t + r * kRowBlock);
+                if (j < A.ncl && e < A.cl_len[j]) v[g][r] = loadv(a + A.cl_lo[j] + e);
             }
 #pragma unroll
         for (int g = 0; g < kGroup; ++g)
 #pragma unroll
             for (int r = 0; r < kStageRounds; ++r) {
-                const int j = j0 + g, e = 2 * (t + r * kRowBlock);
+                const int j = j0 + g, e = V * (t + r * kRowBlock);
                 if (j < A.ncl && e < A.cl_len[j])
-                    *reinterpret_cast<T2*>(sx + A.cl_base[j] + e) = v[g][r];
+                    *reinterpret_cast<TV*>(sx + A.cl_base[j] + e) = v[g][r];
             }
     }
 }
@@ -893,10 +895,10 @@ void plan_lds(sspcg_matrix* A)
     if (nw > kMaxWindows) return;   // too many windows: gathers from memory
     int base = 0;
     for (int j = 0; j < nw; ++j) {
-        const int l = lo[j] & ~1;   // even: windows are copied as aligned pairs
-        int len = hi[j] + kRowBlock - l;
-        len += len & 1;
-        if (len > 2 * kStageRounds * kRowBlock) return;   // longer than the copy covers
+        // multiples of 4: windows are copied as aligned 16-byte vectors
+        const int l = lo[j] & ~3;
+        const int len = (hi[j] + kRowBlock - l + 3) & ~3;
+        if (len > 2 * kStageRounds * kRowBlock) return;   // longer than the FP64 copy covers
         A->cl_lo[j] = l;
         A->cl_len[j] = len;
         A->cl_base[j] = base;
