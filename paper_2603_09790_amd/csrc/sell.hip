@@ -843,14 +843,14 @@ __global__ __launch_bounds__(kRowBlock) void k_mpk_start(int64_t n, const T* __r
 
 int num_cus()
 {
-    static int cus = 0;
-    if (cus == 0) {
-        int dev = 0;
+    // initialised once, thread-safe (solves may run from several host threads)
+    static const int cus = [] {
+        int dev = 0, n = 0;
         hipDeviceProp_t prop;
         if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
-            cus = prop.multiProcessorCount;
-        if (cus <= 0) cus = 256;
-    }
+            n = prop.multiProcessorCount;
+        return n > 0 ? n : 256;
+    }();
     return cus;
 }
 

@@ -495,3 +495,46 @@ def test_graph_replay_matches_eager(poisson5, check_every):
     torch.cuda.synchronize()
     assert il["status"] == P.NOT_CONVERGED and il["outer_iters"] == 13
     assert ile["outer_iters"] == 13 and torch.equal(xl, xle)
+
+
+def test_two_solves_on_one_matrix_at_once():
+    """Solves only read the matrix handle: two solves on one matrix, each with
+    its own workspace and poll buffer, run at once from two host threads on
+    two streams through the C ABI and return the same bits as the same solves
+    run one after the other (the reductions have a fixed order, so running
+    beside another solve changes nothing)."""
+    import ctypes
+    from concurrent.futures import ThreadPoolExecutor
+    from paper_2603_09790_amd import _lib as L
+    from paper_2603_09790_amd import solver as S
+    w = si.workload("diffusion27", N=40)
+    A = w["A"]
+    M = P.Matrix.from_csr(A, device=DEV)
+    bs = [gpu(w["b"]), gpu(si.rhs_uniform(A.n))]
+    opts = dict(s=6, sweeps=2, interval=w["interval"], tol=1e-10)
+    refs = [P.solve(M, b, **opts) for b in bs]
+    p = S._params(6, 2, w["interval"], 1e-10, "fp64", "fgs", 20000, 1e-4, 20, 8)
+    nbytes = ctypes.c_size_t()
+    assert L.lib().sspcg_workspace_bytes(M.handle, ctypes.byref(p), ctypes.byref(nbytes)) == L.OK
+    works = [torch.empty(nbytes.value, dtype=torch.uint8, device=DEV) for _ in bs]
+    polls = [torch.empty(L.POLL_BYTES, dtype=torch.uint8, pin_memory=True) for _ in bs]
+    xs = [torch.zeros(A.n, dtype=torch.float64, device=DEV) for _ in bs]
+    streams = [torch.cuda.Stream(device=DEV) for _ in bs]
+    torch.cuda.synchronize()
+
+    def run(i):
+        res = L.Result()
+        st = L.lib().sspcg_solve(M.handle, ctypes.c_void_p(bs[i].data_ptr()),
+                                 ctypes.c_void_p(xs[i].data_ptr()), ctypes.byref(p),
+                                 ctypes.c_void_p(works[i].data_ptr()), nbytes.value,
+                                 ctypes.c_void_p(polls[i].data_ptr()),
+                                 ctypes.c_void_p(streams[i].cuda_stream), ctypes.byref(res),
+                                 None, None)
+        return st, res.outer_iters
+
+    with ThreadPoolExecutor(2) as ex:
+        out = list(ex.map(run, range(2)))
+    torch.cuda.synchronize()
+    for (st, iters), (xr, ir), x in zip(out, refs, xs):
+        assert st == L.OK and iters == ir["outer_iters"]
+        assert torch.equal(x, xr)
