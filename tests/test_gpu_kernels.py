@@ -764,3 +764,20 @@ def test_update_gram_row_groups_match_single_rows(n):
     gram_close(b0[:, None], b1_[:, None], Qd, r.astype(float)[None, :], tol=1e-13)
     Wr, br = oracle.gram(q0, aq0, r)
     gram_close(w0, Wr, Qd, AQd)
+
+
+# ---------------------------------------------------------------- bandwidth reference
+
+
+@pytest.mark.parametrize("n", [1, 7, 256 * 8 + 3, 1 << 20, (1 << 20) + 1])
+def test_stream_triad(n):
+    """a = b + q c, with q a power of two so that q c is exact and the FMA and
+    the separate product and sum round alike: bit for bit against numpy, also
+    for odd lengths (the last element in a kernel of its own) and lengths
+    that leave a ragged last tile."""
+    rng = np.random.default_rng(60 + n % 97)
+    b, c = rng.normal(size=n), rng.normal(size=n)
+    q = 0.125
+    a = torch.full((n,), np.nan, dtype=torch.float64, device=DEV)
+    P.stream_triad(a, gpu(b), gpu(c), q)
+    assert np.array_equal(host(a), b + q * c)
