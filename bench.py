@@ -443,17 +443,30 @@ COPY_BYTES = 1 << 30   # calibration copy: 1 GiB read + 1 GiB written
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "traffic_k_spmv_27pt_192.json")
 
 
+def code_digest(files) -> str:
+    """SHA-256 of the code of the given C/HIP sources: comments removed and
+    whitespace collapsed, so that only a change of the code itself marks a
+    counter record as stale."""
+    import hashlib
+    import re
+    h = hashlib.sha256()
+    for f in files:
+        s = open(os.path.join(ROOT, f), encoding="utf-8").read()
+        s = re.sub(r"/\*.*?\*/", " ", s, flags=re.S)
+        s = re.sub(r"//[^\n]*", " ", s)
+        h.update(" ".join(s.split()).encode())
+        h.update(b"\0")
+    return h.hexdigest()
+
+
 def counter_traffic():
     """HBM bytes per SpMV launch measured by rocprofv3 counters (FETCH_SIZE,
     WRITE_SIZE, scaled by a copy of known size), from the committed record --
-    or None when the SpMV sources changed since the counters were taken."""
-    import hashlib
+    or None when the code of the SpMV sources changed since the counters were
+    taken."""
     try:
         rec = json.load(open(TRAFFIC_RECORD))
-        h = hashlib.sha256()
-        for f in rec["sources"]:
-            h.update(open(os.path.join(ROOT, f), "rb").read())
-        if h.hexdigest() != rec["source_sha256"]:
+        if code_digest(rec["sources"]) != rec["source_code_sha256"]:
             return None
         return rec["traffic_bytes_per_launch"]
     except (OSError, KeyError, ValueError):
@@ -630,8 +643,7 @@ def traffic_record(fetch_dir: str, write_dir: str, s: int) -> dict:
     """HBM-side bytes per SpMV launch of the matrix powers kernel from the
     FETCH_SIZE and WRITE_SIZE passes (KiB per dispatch) over --mode kernels,
     each scaled by what the same counter reads for the 1 GiB device copy of
-    that run; written to profiles/ with a hash of the SpMV sources."""
-    import hashlib
+    that run; written to profiles/ with a digest of the SpMV sources' code."""
     fetch = counter_rows(fetch_dir, "FETCH_SIZE")
     write = counter_rows(write_dir, "WRITE_SIZE")
     ck = "__amd_rocclr_copyBuffer"     # largest dispatch: the 1 GiB calibration copy
@@ -652,12 +664,9 @@ def traffic_record(fetch_dir: str, write_dir: str, s: int) -> dict:
         raise RuntimeError(f"counter passes lack SpMV modes: found {sorted(modes)}")
     per_launch = (modes[need[1]]["traffic_bytes"] + (s - 2) * modes[need[2]]["traffic_bytes"]
                   + modes[need[0]]["traffic_bytes"]) / s
-    h = hashlib.sha256()
-    for f in TRAFFIC_SOURCES:
-        h.update(open(os.path.join(ROOT, f), "rb").read())
     rec = {"kernel": "k_spmv (matrix powers kernel, FP64)",
            "workload": f"27-point diffusion 192^3, s = {s}",
-           "source_sha256": h.hexdigest(), "sources": TRAFFIC_SOURCES,
+           "source_code_sha256": code_digest(TRAFFIC_SOURCES), "sources": TRAFFIC_SOURCES,
            "calibration": {"kernel": ck + " (1 GiB device copy)", "bytes_each_way": COPY_BYTES,
                            "fetch_kib": fetch[ck], "write_kib": write[ck],
                            "fetch_scale": fscale, "write_scale": wscale},

@@ -105,7 +105,7 @@ struct Sell {
 // arguments for the uniform layout).
 constexpr int kMaxUnion = 32;
 constexpr int kMaxWindows = 12;    // LDS windows of x per tile at most
-constexpr int kStageRounds = 2;    // element pairs each thread copies per window at most
+constexpr int kStageRounds = 2;    // 16-byte vectors each thread copies per window at most
 constexpr int kMaxStaged = 4096;   // staged elements per tile at most (32 KB in FP64)
 static_assert(sizeof(Sell<double>::uo) == kMaxUnion * sizeof(int32_t), "offset list size");
 static_assert(sizeof(Sell<double>::cl_lo) == kMaxWindows * sizeof(int32_t), "window list size");

@@ -15,7 +15,8 @@
 // When one list fits all slices the matrix uses the uniform layout instead
 // (one global list, 16-byte value groups, optionally one triangle of a
 // symmetric matrix, and in FP64 the gathered parts of x staged in LDS as
-// aligned element pairs; see Sell in common.h).  In every kind the entries
+// aligned 16-byte vectors, one window per group of nearby offsets; see Sell
+// in common.h).  In every kind the entries
 // of a row keep their CSR order, which is the summation order, and a zero
 // adds nothing (for finite x): the sum is the CSR sum.
 

@@ -1,6 +1,5 @@
 """Host logic of bench.py (no GPU): the one-GPU guard, the byte models the
 roofline divides by, and the guard on the counter-traffic record."""
-import hashlib
 import json
 import os
 import subprocess
@@ -55,16 +54,19 @@ def test_phase_bytes_follow_the_solve_kernels():
     assert pb["xr"] == (s + 4) * 8 * n                # AQ, r, dinv in; r, z1 out
 
 
-def test_traffic_record_is_ignored_when_the_sources_change(tmp_path, monkeypatch):
+def test_traffic_record_is_ignored_when_the_code_changes(tmp_path, monkeypatch):
     src = tmp_path / "kernel.hip"
-    src.write_text("// kernel v1\n")
-    rec = {"sources": [str(src)], "source_sha256": hashlib.sha256(b"// kernel v1\n").hexdigest(),
+    src.write_text("// kernel v1\nint f() { return 1; }\n")
+    rec = {"sources": [str(src)], "source_code_sha256": bench.code_digest([str(src)]),
            "traffic_bytes_per_launch": 123.0}
     path = tmp_path / "record.json"
     path.write_text(json.dumps(rec))
     monkeypatch.setattr(bench, "TRAFFIC_RECORD", str(path))
     assert bench.counter_traffic() == 123.0
-    src.write_text("// kernel v2\n")
+    # comments and layout do not count
+    src.write_text("// kernel v2, reworded\n/* a block\n comment */ int f()  {\n return 1; }\n")
+    assert bench.counter_traffic() == 123.0
+    src.write_text("// kernel v2\nint f() { return 2; }\n")
     assert bench.counter_traffic() is None
     path.write_text("not json")
     assert bench.counter_traffic() is None
