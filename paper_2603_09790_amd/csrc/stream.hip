@@ -3,10 +3,13 @@
 // 8 TB/s peak is not reached by any access pattern).  Not part of the method.
 //
 // Each thread moves 16-byte vectors with non-temporal loads and stores (the
-// arrays are far larger than the caches, as the solver's blocks are), four
-// vectors of each operand in flight per loop trip; workgroups walk
-// contiguous per-die ranges of 256-vector tiles, as the solver's row
-// kernels do.
+// arrays are far larger than the caches, as the solver's blocks are), one
+// vector of each operand per loop trip, in a grid of two workgroups per CU
+// that walk contiguous per-die ranges of 256-vector tiles.  That shape was
+// the fastest of a sweep over 1, 2, 4 and 8 vectors per trip and 1, 2, 3, 4
+// and 8 workgroups per CU (1 GiB arrays, two devices): 5.9-6.1 TB/s, against
+// 5.1-5.2 TB/s with four vectors per trip and eight workgroups per CU --
+// more bytes in flight per CU made the triad slower, not faster.
 
 #include "launch.h"
 
@@ -14,7 +17,8 @@ namespace sspcg {
 
 namespace {
 
-constexpr int kTriadUnroll = 4;
+constexpr int kTriadUnroll = 1;
+constexpr int kTriadBlocksPerCu = 2;
 typedef double d2 __attribute__((ext_vector_type(2)));
 
 __global__ __launch_bounds__(kRowBlock) void k_triad(int64_t nv, const d2* __restrict__ b,
@@ -64,7 +68,8 @@ int launch_triad(int64_t n, const double* b, const double* c, double q, double* 
     if (nv > 0) {
         const int64_t ntiles = (nv + (int64_t)kTriadUnroll * kRowBlock - 1)
                                / ((int64_t)kTriadUnroll * kRowBlock);
-        const int G = persistent_grid(ntiles, 8, resident_blocks((const void*)k_triad, kRowBlock));
+        const int G = persistent_grid(ntiles, kTriadBlocksPerCu,
+                                      resident_blocks((const void*)k_triad, kRowBlock));
         hipLaunchKernelGGL(k_triad, dim3(G), dim3(kRowBlock), 0, st, nv,
                            reinterpret_cast<const d2*>(b), reinterpret_cast<const d2*>(c), q,
                            reinterpret_cast<d2*>(a));
