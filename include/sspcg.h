@@ -387,10 +387,11 @@ int sspcg_diffusion7_theta_grad(const sspcg_matrix* A, const double* theta, cons
 /* ------------------------------------------------------------ measurement */
 /* STREAM-style triad a = b + q c over n doubles (device arrays, 16-byte
  * aligned; a must not overlap b or c), asynchronous on `stream`.  It moves
- * 24 n bytes with the access pattern of the solver's block kernels
- * (non-temporal 16-byte loads and stores, per-die contiguous ranges): the
- * achievable HBM bandwidth that the kernels' byte rates are set against, next
- * to the published peak.  Not a step of the method.  n = 0 does nothing. */
+ * 24 n bytes with non-temporal 16-byte loads and stores over per-die
+ * contiguous ranges, in the fastest launch shape measured for this pattern:
+ * the achievable HBM bandwidth that the kernels' byte rates are set against,
+ * next to the published peak.  Not a step of the method.  n = 0 does
+ * nothing. */
 int sspcg_stream_triad(int64_t n, const double* b, const double* c, double q, double* a,
                        sspcg_stream stream);
 
