@@ -20,6 +20,9 @@
    64^2 system).
 3. The mixed form at 192^3, refined to a true residual of 1e-12, against the
    oracle's PCG record: the same 1e-10 bar as the FP64 solver.
+4. The differentiable form at its workload's size (7-point diffusion 96^3):
+   the gradient through the device's forward and adjoint solves against the
+   oracle's gradient record (tests/golden/make_gradient_records.py), 1e-10.
 """
 import glob
 import json
@@ -39,6 +42,7 @@ pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
 HERE = os.path.dirname(os.path.abspath(__file__))
 RECORDS = sorted(glob.glob(os.path.join(HERE, "golden", "solutions", "*.json")))
+GRADIENTS = sorted(glob.glob(os.path.join(HERE, "golden", "gradients", "*.json")))
 SOLUTION_TOL = 1e-10
 
 
@@ -167,3 +171,42 @@ def test_mixed_refinement_reaches_1e10_against_oracle_record():
           f"iterations; sampled 2-norm error {est:.2e}, worst sample {worst:.2e}, "
           f"norm {nd:.2e}, projections {pe:.2e}")
     assert max(est, worst, nd, pe) <= SOLUTION_TOL
+
+
+@pytest.mark.parametrize("path", GRADIENTS, ids=[os.path.basename(p)[:-5] for p in GRADIENTS])
+def test_gradient_matches_oracle_record(path):
+    """dL/dtheta of L = 0.5 ||x - x_target||^2, x = A(theta)^{-1} b, through
+    the device's forward and adjoint s-step solves (both to the record's
+    1e-14) and its gradient kernels, against the oracle's: the loss, the
+    sampled entries, the norm and the projections agree to 1e-10."""
+    rec = json.load(open(path))
+    print(f"[gradient record] {rec['case']}: n={rec['n']}", flush=True)
+    w = si.workload(rec["workload"], N=rec["N"])
+    A, theta, b, xt = w["A"], w["theta"], w["b"], w["x_target"]
+    assert (si.digest(theta), si.digest(b), si.digest(xt)) == \
+        (rec["digest_theta"], rec["digest_b"], rec["digest_x_target"])
+    interval = (float.fromhex(rec["interval_hex"][0]), float.fromhex(rec["interval_hex"][1]))
+    M = P.Matrix.from_csr(A, device=DEV)
+    opts = dict(s=rec["s"], sweeps=rec["sweeps"], interval=interval, tol=rec["tol"])
+    th = torch.from_numpy(theta).to(DEV).requires_grad_(True)
+    x = P.DiffusionSolve.apply(th, torch.from_numpy(b).to(DEV), M, opts)
+    loss = 0.5 * torch.sum((x - torch.from_numpy(xt).to(DEV)) ** 2)
+    loss.backward()
+    g = th.grad.detach()
+    idx = si.sample_indices(rec["n"], rec["n_samples"])
+    assert si.digest(idx) == rec["digest_indices"]
+    gs = g[torch.from_numpy(idx).to(DEV)].cpu().numpy()
+    go = np.asarray(rec["g_samples"])
+    d = gs - go
+    est = np.sqrt(rec["n"] / idx.size * np.sum(d * d)) / rec["norm_g"]
+    worst = np.abs(d).max() / np.abs(go).max()
+    ng = torch.linalg.vector_norm(g).item()
+    gh = g.cpu().numpy()
+    V = si.probe_vectors(rec["n"], rec["n_probes"])
+    pe = max(abs(oracle.dot(gh, v) - p) / (rec["norm_g"] * pn)
+             for v, p, pn in zip(V, rec["projections"], rec["probe_norms"]))
+    del V
+    le = abs(loss.item() - rec["loss"]) / rec["loss"]
+    print(f"[gradient record] loss {le:.2e}, sampled 2-norm error {est:.2e}, worst sample "
+          f"{worst:.2e}, norm {abs(ng - rec['norm_g']) / rec['norm_g']:.2e}, projections {pe:.2e}")
+    assert max(le, est, worst, abs(ng - rec["norm_g"]) / rec["norm_g"], pe) <= SOLUTION_TOL
