@@ -882,10 +882,14 @@ void plan_lds(sspcg_matrix* A)
     // tile after the current window's last offset: one window then costs no
     // more LDS and fewer loads than two (the 27-point stencil's three runs
     // of a plane, N apart, share one window when N <= 256)
+    // (a merge that would make a window longer than the copy covers starts a
+    // new window instead)
+    constexpr int kMaxLen = 2 * kStageRounds * kRowBlock;
+    auto span = [](int l, int h) { return ((h + kRowBlock - (l & ~3)) + 3) & ~3; };
     int lo[kMaxUnion], hi[kMaxUnion], win[kMaxUnion];
     int nw = 0;
     for (int k = 0; k < A->uw; ++k) {
-        if (nw == 0 || o[k] - hi[nw - 1] > kRowBlock) {
+        if (nw == 0 || o[k] - hi[nw - 1] > kRowBlock || span(lo[nw - 1], o[k]) > kMaxLen) {
             lo[nw] = hi[nw] = o[k];
             ++nw;
         } else {
@@ -898,8 +902,8 @@ void plan_lds(sspcg_matrix* A)
     for (int j = 0; j < nw; ++j) {
         // multiples of 4: windows are copied as aligned 16-byte vectors
         const int l = lo[j] & ~3;
-        const int len = (hi[j] + kRowBlock - l + 3) & ~3;
-        if (len > 2 * kStageRounds * kRowBlock) return;   // longer than the FP64 copy covers
+        const int len = span(lo[j], hi[j]);
+        if (len > kMaxLen) return;   // one run longer than the FP64 copy covers
         A->cl_lo[j] = l;
         A->cl_len[j] = len;
         A->cl_base[j] = base;

@@ -713,13 +713,19 @@ def banded_csr(n, offsets, seed):
 
 
 @pytest.mark.parametrize("nruns", [11, 13])
+@pytest.mark.parametrize("spacing", ["near", "far"])
 @pytest.mark.parametrize("full", [False, True])
-def test_many_offset_runs(nruns, full):
+def test_many_offset_runs(nruns, spacing, full):
     """2k+1 isolated offsets (a mirrored list always has an odd number of
-    runs): up to 12 runs x is staged in LDS (FP64), beyond that the rows
-    gather from memory; both must give the oracle's product and iterates."""
+    runs).  Near offsets (less than a tile apart) share one LDS window of x;
+    far ones (more than a tile apart) take a window each: up to 12 windows x
+    is staged in LDS (FP64), beyond that the rows gather from memory.  Every
+    case must give the oracle's product and iterates."""
     k = (nruns - 1) // 2
-    offsets = [3 * (i + 1) + i * i for i in range(k)]            # no two consecutive
+    if spacing == "near":
+        offsets = [3 * (i + 1) + i * i for i in range(k)]        # no two consecutive
+    else:
+        offsets = [257 * (i + 1) + i for i in range(k)]          # gaps beyond a tile
     n = 64 * 37 + 11
     A = banded_csr(n, offsets, seed=46 + nruns)
     M = P.Matrix.from_csr(A, fp32=True, full_storage=full, device=DEV)
