@@ -399,4 +399,8 @@ def workload(name: str, N: int | None = None) -> dict:
         b = rhs_uniform(A.n)
         return dict(A=A, b=b, s=4, sweeps=2, interval=lanczos_bounds(A), tol=1e-8,
                     theta=theta, x_target=x_target(A.n))
+    if name == "hpcg27":            # the paper's per-GPU share: HPCG 27-point, b = 1
+        N = N or 200
+        A = hpcg27(N)
+        return dict(A=A, b=np.ones(A.n), s=4, sweeps=30, interval=power_bounds(A), tol=1e-8)
     raise ValueError(f"unknown workload {name!r}")

@@ -11,6 +11,8 @@ host cores):
   the 192^3 workload, whose records also stand in for the full solution in
   the benchmark's error report);
 * x^T v for the 8 vectors of ``sspcg_inputs.probe_vectors``;
+* for the paper's own workload (HPCG 27-point 200^3, b = 1, power-method
+  interval), the Gram solve used: 30 FGS sweeps, or the Cholesky solve;
 * the basis interval the solve used (exact, as float.hex), and digests of
   the matrix values and the right-hand side, so that a test can tell whether
   it rebuilt the same system.
@@ -71,6 +73,11 @@ def _cases() -> dict:
     c["diffusion27_192_s6_nu2"] = dict(workload="diffusion27", N=192, method="sspcg", s=6,
                                        sweeps=2, samples=16384)
     c["diffusion27_192_pcg"] = dict(workload="diffusion27", N=192, method="pcg", samples=16384)
+    # the paper's own workload (HPCG 27-point 200^3, b = 1, lambda_min = 0 and
+    # power-method lambda_max): FGS with 30 sweeps and the Cholesky Gram solve
+    c["hpcg27_200_s4_nu30"] = dict(workload="hpcg27", N=200, method="sspcg", s=4, sweeps=30)
+    c["hpcg27_200_s6_cholesky"] = dict(workload="hpcg27", N=200, method="sspcg", s=6,
+                                       sweeps=1, gram="cholesky")
     return c
 
 
@@ -90,7 +97,7 @@ def make(case: str) -> dict:
     if spec["method"] == "sspcg":
         tol = SSTEP_TOL
         x, res = oracle.sspcg(A, b, s=spec["s"], sweeps=spec["sweeps"], interval=interval,
-                              tol=tol, max_outer=100000)
+                              tol=tol, max_outer=100000, gram=spec.get("gram", "fgs"))
     else:
         tol = PCG_TOL
         x, res = oracle.pcg(A, b, tol=tol, max_iter=200000)
@@ -99,11 +106,12 @@ def make(case: str) -> dict:
     V = si.probe_vectors(A.n, N_PROBES)
     rec = dict(
         case=case,
-        what=("oracle s-step PCG (Algorithm 1, Chebyshev basis, FGS Gram solves)"
+        what=(f"oracle s-step PCG (Algorithm 1, Chebyshev basis, "
+              f"{'Cholesky' if spec.get('gram') == 'cholesky' else 'FGS'} Gram solves)"
               if spec["method"] == "sspcg" else "oracle classical Jacobi PCG"),
         command=f"python tests/golden/make_solution_records.py --case {case}",
         workload=spec["workload"], N=spec["N"], n=A.n, nnz=A.nnz, method=spec["method"],
-        s=spec.get("s"), sweeps=spec.get("sweeps"),
+        s=spec.get("s"), sweeps=spec.get("sweeps"), gram=spec.get("gram", "fgs"),
         interval_hex=[interval[0].hex(), interval[1].hex()], interval=list(interval),
         tol=tol,
         digest_val=si.digest(A.val), digest_b=si.digest(b),
