@@ -11,8 +11,9 @@ host cores):
   the 192^3 workload, whose records also stand in for the full solution in
   the benchmark's error report);
 * x^T v for the 8 vectors of ``sspcg_inputs.probe_vectors``;
-* for the paper's own workload (HPCG 27-point 200^3, b = 1, power-method
-  interval), the Gram solve used: 30 FGS sweeps, or the Cholesky solve;
+* the Gram solve and basis: for the paper's own workload (HPCG 27-point
+  200^3, b = 1, power-method interval) 30 FGS sweeps or the Cholesky solve;
+  adaptive sweeps on the 192^3 system; the monomial basis on 128^3;
 * the basis interval the solve used (exact, as float.hex), and digests of
   the matrix values and the right-hand side, so that a test can tell whether
   it rebuilt the same system.
@@ -78,6 +79,13 @@ def _cases() -> dict:
     c["hpcg27_200_s4_nu30"] = dict(workload="hpcg27", N=200, method="sspcg", s=4, sweeps=30)
     c["hpcg27_200_s6_cholesky"] = dict(workload="hpcg27", N=200, method="sspcg", s=6,
                                        sweeps=1, gram="cholesky")
+    # adaptive sweeps on the benchmark system (stop sweeping once
+    # ||m - W a|| <= 1e-3 ||m||, at most 30 sweeps) and the monomial basis
+    # on the 7-point Poisson 128^3 system
+    c["diffusion27_192_s6_adaptive"] = dict(workload="diffusion27", N=192, method="sspcg", s=6,
+                                            sweeps=30, sweep_tol=1e-3)
+    c["poisson7_128_s2_nu3_monomial"] = dict(workload="poisson7", N=128, method="sspcg", s=2,
+                                             sweeps=3, basis="monomial")
     return c
 
 
@@ -97,7 +105,9 @@ def make(case: str) -> dict:
     if spec["method"] == "sspcg":
         tol = SSTEP_TOL
         x, res = oracle.sspcg(A, b, s=spec["s"], sweeps=spec["sweeps"], interval=interval,
-                              tol=tol, max_outer=100000, gram=spec.get("gram", "fgs"))
+                              tol=tol, max_outer=100000, gram=spec.get("gram", "fgs"),
+                              sweep_tol=spec.get("sweep_tol", 0.0),
+                              basis=spec.get("basis", "chebyshev"))
     else:
         tol = PCG_TOL
         x, res = oracle.pcg(A, b, tol=tol, max_iter=200000)
@@ -112,6 +122,7 @@ def make(case: str) -> dict:
         command=f"python tests/golden/make_solution_records.py --case {case}",
         workload=spec["workload"], N=spec["N"], n=A.n, nnz=A.nnz, method=spec["method"],
         s=spec.get("s"), sweeps=spec.get("sweeps"), gram=spec.get("gram", "fgs"),
+        sweep_tol=spec.get("sweep_tol", 0.0), basis=spec.get("basis", "chebyshev"),
         interval_hex=[interval[0].hex(), interval[1].hex()], interval=list(interval),
         tol=tol,
         digest_val=si.digest(A.val), digest_b=si.digest(b),

@@ -3,8 +3,9 @@
 1. Against the oracle's committed solution records (written by
    tests/golden/make_solution_records.py from the CPU oracle alone): the
    2D Poisson 64^2 system, the 7-point Poisson 128^3 (s, nu) grid, the
-   27-point heterogeneous 192^3 benchmark system and the paper's own
-   workload (HPCG 27-point 200^3, b = 1) with 30 FGS sweeps and with the
+   27-point heterogeneous 192^3 benchmark system (also with adaptive
+   sweeps), the 7-point 128^3 system in the monomial basis, and the paper's
+   own workload (HPCG 27-point 200^3, b = 1) with 30 FGS sweeps and with the
    Cholesky Gram solve.  Both sides run
    Algorithm 1 with the same interval, s and nu to the record's relative
    residual (1e-14; classical PCG 1e-13): two correct solves to tau differ by
@@ -86,7 +87,9 @@ def test_solution_matches_oracle_record(path):
     bd = torch.from_numpy(b).to(DEV)
     if rec["method"] == "sspcg":
         x, info = P.solve(M, bd, s=rec["s"], sweeps=rec["sweeps"], interval=interval,
-                          tol=rec["tol"], max_outer=100000, gram=rec.get("gram", "fgs"))
+                          tol=rec["tol"], max_outer=100000, gram=rec.get("gram", "fgs"),
+                          sweep_tol=rec.get("sweep_tol", 0.0),
+                          basis=rec.get("basis", "chebyshev"))
     else:
         x, info = P.pcg(M, bd, tol=rec["tol"], max_iter=200000)
     assert info["status"] == P.OK and rec["status"] == 0
