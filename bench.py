@@ -422,6 +422,19 @@ def main() -> int:
     if args.N == 192 and s == 6 and args.sweeps == 2:
         out["to_1e-10_vs_oracle"] = accuracy_vs_oracle(P, M, b, A, b_np, interval, args,
                                                        with_mixed=not args.no_mixed)
+    # the same system with other Gram solves (outside the timed steps): the
+    # exact Cholesky solve and adaptive FGS sweeps (stop once
+    # ||m - W a|| <= 1e-3 ||m||, at most 30), FP64 and mixed
+    variants = {}
+    for name, kw in (("cholesky", dict(sweeps=1, gram="cholesky")),
+                     ("fgs_adaptive_1e-3", dict(sweeps=30, sweep_tol=1e-3))):
+        variants[name] = {}
+        for prec in ("fp64",) + (() if args.no_mixed else ("mixed",)):
+            _, iv = P.solve(M, b, s=args.s, interval=interval, tol=args.tol, precision=prec, **kw)
+            variants[name][prec] = {"time_s": iv["device_ms"] / 1e3, "status": iv["status_name"],
+                                    "outer_iters" if prec == "fp64" else "inner_iters":
+                                        iv["outer_iters"]}
+    out["gram_solve_variants"] = variants
     # classical PCG comparator on the same system (outside the timed steps)
     _, ip = P.pcg(M, b, tol=args.tol)
     out["pcg"] = {"time_s": ip["device_ms"] / 1e3, "iters": ip["outer_iters"],
