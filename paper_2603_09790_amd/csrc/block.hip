@@ -445,12 +445,7 @@ int launch_update_gram(int64_t n, int s, const T* Z, T* Q, const T* AZ, T* AQ, c
     // as 16-byte vectors measured the same (402-411 vs 407-409 us); the
     // kernel already streams at the rate a copy or triad reaches on these
     // boxes for its mix of reads and writes (12 of 37 columns written).
-    // FP64 runs one workgroup per CU: with its 26 read and 13 written
-    // streams that was 0.8 % faster than two (the other block kernels are
-    // faster with two); the virtual blocks keep the sums, and the iterates,
-    // the same for either grid.
     constexpr int RV = sizeof(T) == 4 ? 4 : 1;
-    constexpr int kUpdateBlocksPerCu = sizeof(T) == 4 ? 8 : 1;
     auto a16 = [](const void* p) { return p == nullptr || reinterpret_cast<uintptr_t>(p) % 16 == 0; };
     const bool vec = RV > 1 && ld % RV == 0 && a16(Z) && a16(Q) && a16(AZ) && a16(AQ) && a16(r) &&
                      a16(x);
@@ -460,7 +455,7 @@ int launch_update_gram(int64_t n, int s, const T* Z, T* Q, const T* AZ, T* AQ, c
     switch (s) {
 #define L(S, M, R)                                                                               \
     do {                                                                                         \
-        G = block_grid(units, k_update_gram<S, T, M, R>, kUpdateBlocksPerCu);                   \
+        G = block_grid(units, k_update_gram<S, T, M, R>);                                       \
         hipLaunchKernelGGL((k_update_gram<S, T, M, R>), dim3(G), dim3(kRowBlock), 0, st, n, ld,  \
                            Z, Q, AZ, AQ, beta, r, x, alpha, partials, ctrl);                     \
     } while (0)
